@@ -1,0 +1,204 @@
+/*
+ * ptamd: MI355X (gfx950) library for the fast molecular-dynamics bursts of
+ * Practical Time Averaging (PTA), after Baruah, Chatterjee, Acharya and Wang,
+ * "Averaging Molecular Dynamics simulations to study the slow-strain-rate
+ * behavior of metals".
+ *
+ * One call of ptamd_run_fast_md() is one PTA averaging burst: it holds the
+ * load fixed, runs n velocity-Verlet steps of EAM dynamics of a free-surface
+ * FCC aluminium cube and returns the running time averages of the kinetic
+ * energy, the potential energy and the sigma_zz virial stress
+ * (Sec. 2.2 Step 1, Eq. (R_m_t); state functions of Eq. (state_variables)).
+ * ptamd_apply_strain_increment() moves the load between bursts (Sec. 2.4.2,
+ * the loading sequence).
+ *
+ * Conventions for every entry point:
+ *   - Units: Angstrom, eV, fs, amu, K; stresses in GPa (tension positive).
+ *   - The load axis is z.  Arrays at the boundary are host arrays in the
+ *     ORIGINAL atom order (the lattice order of ptamd_create_system, or the
+ *     caller's order for ptamd_create_system_from_state); the library's
+ *     internal spatial ordering is never visible.
+ *   - The caller owns every host buffer it passes; each must hold at least
+ *     the stated number of elements.  The library never keeps a host pointer
+ *     after a call returns.  The library owns all device memory of a system.
+ *   - Every function returns a ptamd_status; 0 is success.  On failure,
+ *     ptamd_last_error() returns a message (thread local, valid until the
+ *     next call on the same thread).  After an error other than
+ *     PTAMD_EINVAL the system stays valid, but its state may be partly
+ *     advanced: restore it with ptamd_set_state().
+ *   - A system is not thread safe: one thread at a time per handle.
+ *   - All device work is ordered on the system's HIP stream (the null
+ *     stream unless ptamd_set_stream() names another).  Every call returns
+ *     after its results are on the host.
+ *   - There is no CPU fallback: without a usable gfx950 device every call
+ *     that needs one returns PTAMD_ENODEV.
+ */
+#ifndef PTAMD_H
+#define PTAMD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ptamd_system ptamd_system; /* opaque */
+
+typedef enum {
+    PTAMD_OK = 0,
+    PTAMD_EINVAL = -1,     /* bad argument: nothing was changed */
+    PTAMD_EDEVICE = -2,    /* a HIP runtime call failed */
+    PTAMD_ENOMEM = -3,     /* device or host allocation failed */
+    PTAMD_ENONFINITE = -4, /* a position, velocity or energy became NaN/Inf */
+    PTAMD_EESCAPE = -5,    /* an atom left the allowed region around the cube */
+    PTAMD_EOVERFLOW = -6,  /* an internal capacity could not be grown */
+    PTAMD_ESTATE = -7,     /* thermostat met T <= 0, or lambda^2 < 0 */
+    PTAMD_ENODEV = -8      /* no usable gfx950 device */
+} ptamd_status;
+
+/* Free-surface FCC cube of n_cells^3 conventional cells (4 atoms each) with
+ * axes along [100],[010],[001] (Sec. 2.4.1 "Problem Setup").  Lattice
+ * positions are integer plane indices times lattice_a/2.  Initial velocities
+ * are Maxwell-Boltzmann at T0 (Sec. 2.4.2): normals from the counter-based
+ * SplitMix64 stream of `seed` via Box-Muller, three per atom in atom order,
+ * mobile atoms only, mean removed, rescaled to T0 with 3*N_mob-3 degrees of
+ * freedom.  T0 is also the thermostat target.  With fix_slabs != 0 the
+ * three lowest and three highest z planes are the fixed boundary regions
+ * (v = 0, F = 0; Sec. 2.4.2); n_cells >= 4 then, else n_cells >= 1. */
+typedef struct {
+    int32_t n_cells;
+    double lattice_a;
+    double T0;
+    uint64_t seed;
+    int32_t fix_slabs;
+} ptamd_lattice_desc;
+
+/* Sutton-Chen functions in the EAM energy of Eq. (pe):
+ *   V(r) = eps (a/r)^n,  rho(r) = (a/r)^m,  B(rhobar) = -c eps sqrt(rhobar),
+ * cut at rc (strict r < rc).  shift: 0 truncated, 1 energy-shifted,
+ * 2 shifted-force (value and slope of V and rho vanish at rc).
+ * Requires eps >= 0, a > 0, n > 0, m > 0, c >= 0, 0 < rc <= 4a. */
+typedef struct {
+    double eps, a, n, m, c, rc;
+    int32_t shift;
+} ptamd_sc_params;
+
+/* precision: 0 = FP64 everywhere; 1 = mixed (pair and density terms in FP32;
+ * state, forces-to-velocity update and all global sums in FP64 / 64-bit fixed
+ * point).  skin: Verlet-list skin in A (0 < skin <= 3).  lanes_per_atom:
+ * 0 = autotune, else one of 1, 2, 4, 8, 16.  thermostat: 0 = NVE,
+ * 1 = Berendsen with coupling time tau_fs (> 0), applied to the mobile atoms
+ * at the end of each step. */
+typedef struct {
+    double dt_fs;
+    double tau_fs;
+    int32_t thermostat;
+    int32_t precision;
+    double skin;
+    int32_t lanes_per_atom;
+} ptamd_md_params;
+
+/* Burst averages over the samples r = 1..n (Eq. (R_m_t)); *_se are
+ * standard errors from 20 equal blocks (NaN below 20 samples); tz is the
+ * reaction stress -sum_{top} F^int_z / area0 of Eq. (state_variables) read
+ * along z; strain is the engineering strain at which the burst ran. */
+typedef struct {
+    double ke, pe, szz, tz;
+    double ke_se, pe_se, szz_se;
+    double temp;
+    double strain;
+    int64_t n_samples;
+} ptamd_averages;
+
+typedef struct {
+    int64_t n_atoms;         /* all replicas */
+    int32_t n_replicas;
+    int32_t precision;
+    int32_t lanes_per_atom;
+    int32_t list_capacity;   /* per-atom Verlet-list capacity */
+    int64_t list_builds;     /* since creation */
+    int64_t sorts;           /* spatial re-sorts since creation */
+    int64_t rollbacks;       /* chunks re-run after a failed bound */
+    int64_t steps;           /* MD steps since creation */
+    double skin;
+    double bin_margin;
+} ptamd_info;
+
+/* ---- creation ---- */
+ptamd_status ptamd_create_system(const ptamd_lattice_desc *desc, const ptamd_sc_params *sc,
+                                 const ptamd_md_params *md, ptamd_system **out);
+/* A system from an explicit state (n atoms; group[i]: 0 mobile, 1 fixed
+ * bottom region, 2 fixed top region, whose internal z force is the
+ * reaction).  volume0 (A^3, at zero strain) scales the virial stress,
+ * area0 (A^2) the reaction stress; T0 is the thermostat target. */
+ptamd_status ptamd_create_system_from_state(int64_t n, const double *x, const double *y, const double *z,
+                                            const double *vx, const double *vy, const double *vz,
+                                            const uint8_t *group, double volume0, double area0, double T0,
+                                            const ptamd_sc_params *sc, const ptamd_md_params *md,
+                                            ptamd_system **out);
+/* R independent replicas in one system (one launch per kernel covers them
+ * all).  Replica r is the cube of descs[r]; its thermostat target is
+ * descs[r].T0.  Atoms are numbered replica by replica. */
+ptamd_status ptamd_create_batch(int32_t n_replicas, const ptamd_lattice_desc *descs, const ptamd_sc_params *sc,
+                                const ptamd_md_params *md, ptamd_system **out);
+ptamd_status ptamd_destroy_system(ptamd_system *sys);
+
+/* ---- the hot path ---- */
+/* Load step along z about z = 0 (Sec. 2.4.2 loading sequence, applied as an
+ * affine strain of every atom): eps_k = eps_{k-1} + d_eps, every z scaled by
+ * (1+eps_k)/(1+eps_{k-1}); velocities unchanged; fixed regions stay fixed at
+ * their new positions.  |d_eps| < 0.05.  Applies to every replica. */
+ptamd_status ptamd_apply_strain_increment(ptamd_system *sys, double d_eps);
+/* Per-replica increments: d_eps has n_replicas entries. */
+ptamd_status ptamd_apply_strain_increments(ptamd_system *sys, const double *d_eps);
+/* One averaging burst of n_steps >= 1 steps (Sec. 2.3 velocity Verlet,
+ * Eqs. (vv_algo_pos_pred_half), (vv_algo_pos_pred), (vv_algo_vel_pred), with
+ * fixed regions and the optional Berendsen thermostat).  Forces are
+ * recomputed from the positions at the start.  out has n_replicas entries. */
+ptamd_status ptamd_run_fast_md(ptamd_system *sys, int64_t n_steps, ptamd_averages *out);
+
+/* ---- state in and out (original order, all replicas concatenated) ---- */
+ptamd_status ptamd_get_num_atoms(const ptamd_system *sys, int64_t *n);
+ptamd_status ptamd_get_state(ptamd_system *sys, double *x, double *y, double *z, double *vx, double *vy,
+                             double *vz);
+ptamd_status ptamd_set_state(ptamd_system *sys, const double *x, const double *y, const double *z,
+                             const double *vx, const double *vy, const double *vz);
+ptamd_status ptamd_get_strain(const ptamd_system *sys, double *strain /* n_replicas */);
+
+/* ---- inspection hooks for tests ---- */
+/* Internal forces F^int of Eq. (f_int) before any constraint, at the current
+ * positions, plus per-replica U (Eq. (pe)) and W_zz = sum_i z_i F_iz.
+ * pe and wzz have n_replicas entries. */
+ptamd_status ptamd_compute_forces(ptamd_system *sys, double *fx, double *fy, double *fz, double *pe,
+                                  double *wzz);
+/* Spatially sorts and rebuilds the Verlet list at the current positions and
+ * returns it as CSR in original indices, each row ascending: offsets has
+ * n+1 entries, idx has cap entries.  Returns PTAMD_EOVERFLOW (with
+ * offsets filled) if cap is too small. */
+ptamd_status ptamd_get_neighbors(ptamd_system *sys, int64_t *offsets, int32_t *idx, int64_t cap);
+/* Cell coordinates (3 per atom, original order) of the last spatial sort,
+ * and per replica its grid origin (3), 1/h and dims (3). */
+ptamd_status ptamd_get_cells(ptamd_system *sys, int32_t *cxyz, double *origin, double *inv_h, int32_t *dims);
+/* Per-step samples of the last burst for replica r, row major with 6
+ * columns: K, U, sigma_zz, T, lambda, T_z.  cap = rows the buffer holds. */
+ptamd_status ptamd_get_series(ptamd_system *sys, int32_t replica, double *buf, int64_t cap);
+ptamd_status ptamd_get_info(const ptamd_system *sys, ptamd_info *info);
+
+/* ---- streams and timing ---- */
+/* Orders all later device work on stream (a hipStream_t, e.g. torch's
+ * current stream on ROCm).  NULL selects the null stream. */
+ptamd_status ptamd_set_stream(ptamd_system *sys, void *hip_stream);
+/* Average duration in ms of the force kernel over the launches it timed with
+ * HIP events on the system's stream since the last reset, and the count. */
+ptamd_status ptamd_kernel_timing(ptamd_system *sys, double *avg_ms, int64_t *count, int32_t reset);
+/* Unique pairs within rc at the current positions (for the algorithmic
+ * flop count), per replica summed. */
+ptamd_status ptamd_count_pairs(ptamd_system *sys, int64_t *pairs_in_rc, int64_t *list_entries);
+
+const char *ptamd_last_error(void);
+const char *ptamd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
