@@ -1,0 +1,144 @@
+// Internal declarations shared by the device kernels and the host runtime.
+// POD structs only: they are passed by value to kernels or live in device
+// memory with the same layout on both sides.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ptamd {
+
+constexpr int kBlock = 256;     // threads per block for every kernel
+constexpr int kTile = 256;      // atoms per replica tile (replica ranges are padded to this)
+constexpr int kSlots = 64;      // spread factor of the fixed-point reduction slots
+constexpr int kNQ = 8;          // reduced quantities per slot
+constexpr int kSeriesCols = 6;  // K, U, sigma_zz, T, lambda, T_z
+constexpr int kSEBlocks = 20;   // blocks of the standard-error estimate
+constexpr uint8_t kPad = 255;   // group tag of padding atoms
+constexpr double kFix = 68719476736.0;  // 2^36: fixed-point scale of global sums
+
+// quantities reduced into the slots
+enum : int {
+  Q_MV2 = 0,   // sum_mob m v^2 (eV), after the second half kick, before lambda
+  Q_MVZ2 = 1,  // sum_mob m v_z^2 (eV)
+  Q_EPAIR = 2, // 1/2 sum_i sum_j V_s(r_ij) (eV)
+  Q_WZZ = 3,   // W_zz = -1/2 sum_i sum_j g_ij dz^2 / r (eV)
+  Q_RZ = 4,    // -sum_{top} F^int_z (eV/A)
+  Q_EMB = 5,   // sum_i B(rhobar_i) (eV)
+  Q_PAIRS = 6, // pairs within rc (directed), diagnostic
+  Q_SPARE = 7
+};
+
+// error bits of Control::err
+enum : int {
+  E_NONFINITE = 1,
+  E_ESCAPE = 2,
+  E_OVERFLOW = 4,  // Verlet list capacity exceeded
+  E_DRIFT = 8,     // an atom drifted beyond the binning margin before a list build
+  E_STATE = 16     // thermostat: T <= 0 or lambda^2 < 0
+};
+
+// Device-resident control block (one per system).
+struct Control {
+  int64_t base;      // absolute step index of the first step in the current chunk
+  int32_t rebuild;   // nonzero: the next density pass rebuilds the Verlet lists
+  int32_t err;       // error bits
+  int64_t n_steps;   // steps of the current burst
+  int64_t se_block;  // samples per standard-error block (n_steps / 20)
+  int32_t list_builds;
+  int32_t pad0;
+};
+
+// Per-replica constants and grid (device memory, read by kernels).
+struct RepInfo {
+  int64_t abeg, aend;   // padded atom range in the sorted arrays
+  int64_t nreal;        // real atoms
+  int64_t nmob;         // mobile atoms
+  double T0, dof;       // thermostat target (K), 3 N_mob - 3
+  double volume0, area0, strain;
+  double origin[3];     // binning grid origin
+  double inv_h;         // 1 / bin edge
+  int32_t dims[3];
+  int32_t pad1;
+  int64_t cell_off;     // offset of this replica's cells in the global cell arrays
+  int64_t ncells;       // dims product (+1 virtual cell for padding atoms)
+  double center[3];     // nominal cube centre (escape test)
+};
+
+// Per-replica burst accumulators (device memory).
+struct RepAcc {
+  double sum[kSeriesCols];
+  double blk[kSEBlocks][3];
+  int64_t nsamp;
+  double lam_last;
+  double out[12];  // ke, pe, szz, tz, ke_se, pe_se, szz_se, temp, strain, n, spare...
+};
+
+// Values uniform over the launch, passed by value.
+struct Params {
+  // potential (FP64 master copies)
+  double eps, a, rc, rc2, c_eps;
+  int32_t n, m;        // integer exponents of V and rho
+  double Vc, dVc, rhoc, drhoc;  // effective shift constants (0 where the mode has none)
+  // lists and binning
+  double rlist2;       // (rc + skin)^2
+  double half_skin2;   // (skin/2)^2: displacement that triggers a list rebuild
+  double margin2;      // binning margin^2
+  double esc2;         // squared escape radius around the replica centre
+  // integrator
+  double dt, hdt_m, tau;
+  int32_t thermostat;
+  int32_t n_rep;
+  double mvv2e_m;      // m * mvv2e (eV per (A/fs)^2)
+  double kb, gpa;
+  int64_t ntot;        // padded atoms, all replicas
+  int64_t nbr_stride;  // ntot * lanes_per_atom
+  int32_t cap_slots;   // list slots per lane
+  int32_t lpa;
+};
+
+// Device buffers (pointers), passed by value.
+struct Buffers {
+  double *x, *y, *z, *vx, *vy, *vz, *fx, *fy, *fz;
+  void *pos4;          // float4 or double4: x, y, z, B'
+  uint8_t *group;
+  int32_t *orig;       // original global index of each sorted atom
+  int32_t *cell;       // linear cell index (within the replica grid) at the last sort
+  float *xs, *ys, *zs; // positions at the last sort
+  float *xr, *yr, *zr; // positions at the last list build
+  int32_t *nbr;        // Verlet lists, [slot][atom*lpa + lane]
+  int32_t *ncount;     // list length per atom
+  int32_t *cell_start; // global cell arrays: [cell_off + c]
+  int32_t *cell_count;
+  int32_t *blk_rep;    // replica of each tile
+  RepInfo *rep;
+  RepAcc *acc;
+  unsigned long long *slots;  // [2][n_rep][kSlots][kNQ]
+  unsigned long long *stat;   // [n_rep][kSlots][4] max-reductions (bit patterns of non-negative doubles)
+  double *series;      // [n_rep][series_cap][kSeriesCols]
+  int64_t series_cap;
+  Control *ctl;
+};
+
+// ---- launch wrappers (kernels.hip) ----
+void launch_burst_begin(const Params &p, const Buffers &b, int n_rep, hipStream_t s);
+void launch_kick_drift(const Params &p, const Buffers &b, int precision, int32_t k, int32_t mode, hipStream_t s);
+void launch_pos4(const Params &p, const Buffers &b, int precision, hipStream_t s);
+void launch_density(const Params &p, const Buffers &b, int precision, int lpa, int32_t k, hipStream_t s);
+void launch_force(const Params &p, const Buffers &b, int precision, int lpa, int32_t k, int32_t mode,
+                  hipStream_t s);
+void launch_set_base(const Buffers &b, int64_t base, hipStream_t s);
+void launch_chunk_stats(const Params &p, const Buffers &b, hipStream_t s);
+void launch_bbox(const Params &p, const Buffers &b, hipStream_t s);
+void launch_assign_count(const Params &p, const Buffers &b, int32_t *key, hipStream_t s);
+void launch_scan_cells(const Params &p, const Buffers &b, int32_t *cursor, hipStream_t s);
+void launch_scatter(const Params &p, const Buffers &b, const int32_t *key, int32_t *cursor, int32_t *tmp,
+                    hipStream_t s);
+void launch_cell_sort(const Params &p, const Buffers &b, const int32_t *tmp, int32_t *perm, int64_t ncells_tot,
+                      hipStream_t s);
+void launch_permute(const Params &p, const Buffers &b, const Buffers &scratch, const int32_t *perm,
+                    const int32_t *key, int precision, hipStream_t s);
+void launch_strain(const Params &p, const Buffers &b, const double *factor, hipStream_t s);
+void launch_fill_i64(unsigned long long *ptr, int64_t n, unsigned long long v, hipStream_t s);
+void launch_count_pairs(const Params &p, const Buffers &b, int precision, hipStream_t s);
+
+}  // namespace ptamd

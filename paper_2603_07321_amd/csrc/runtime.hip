@@ -1,0 +1,1100 @@
+// Host runtime: device memory of a system, the spatial sort, the chunked
+// burst runner (HIP graphs of whole MD steps, with roll-back when a bound
+// that the lists rely on is exceeded), and the C ABI of include/ptamd.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/ptamd.h"
+#include "lattice.h"
+#include "ptamd_internal.h"
+
+namespace ptamd {
+
+struct Failure {
+  ptamd_status code;
+  std::string msg;
+};
+
+[[noreturn]] static void fail(ptamd_status c, const std::string &m) { throw Failure{c, m}; }
+
+#define HIPCHK(expr)                                                                                   \
+  do {                                                                                                 \
+    hipError_t e_ = (expr);                                                                            \
+    if (e_ != hipSuccess) fail(PTAMD_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));      \
+  } while (0)
+
+static thread_local std::string g_last_error;
+
+template <class T> static T *dalloc(size_t n) {
+  if (n == 0) n = 1;
+  void *p = nullptr;
+  hipError_t e = hipMalloc(&p, n * sizeof(T));
+  if (e != hipSuccess) fail(PTAMD_ENOMEM, "hipMalloc of " + std::to_string(n * sizeof(T)) + " bytes failed");
+  return static_cast<T *>(p);
+}
+
+static void dfree(void *p) {
+  if (p) (void)hipFree(p);
+}
+
+constexpr int kMaxDims = 64;       // binning grid cells per axis (atoms beyond are clamped into edge cells)
+constexpr int kMaxChunk = 256;     // steps per captured graph
+constexpr int kMinChunk = 4;
+constexpr int kStartChunk = 64;
+
+struct RepHost {
+  int64_t abeg = 0, aend = 0, nreal = 0, nmob = 0;
+  int64_t orig_base = 0;  // first original index of this replica
+  double T0 = 0, volume0 = 0, area0 = 0, strain = 0;
+  double center[3] = {0, 0, 0};
+  double origin[3] = {0, 0, 0};
+  double inv_h = 0;
+  int dims[3] = {1, 1, 1};
+  int64_t cell_off = 0, ncells = 0;
+};
+
+struct GraphEntry {
+  hipGraphExec_t exec = nullptr;
+};
+
+}  // namespace ptamd
+
+using namespace ptamd;
+
+struct ptamd_system {
+  int device = 0;
+  int n_rep = 1;
+  int precision = 0;
+  int lpa = 1;
+  int cap = 0;  // per-atom list capacity (multiple of lpa)
+  double skin = 1.0, margin = 1.0, bin_h = 0.0;
+  ptamd_sc_params sc{};
+  ptamd_md_params md{};
+  Params P{};
+  Buffers B{};   // primary
+  Buffers S{};   // permutation scratch
+  int64_t ntot = 0, nreal = 0;
+  std::vector<RepHost> reps;
+  std::vector<int32_t> blk_rep_h;
+  int32_t *d_key = nullptr, *d_cursor = nullptr, *d_tmp = nullptr, *d_perm = nullptr;
+  int64_t cells_cap = 0;
+  // snapshot for roll-back
+  double *snap = nullptr;  // 9 arrays of ntot doubles
+  unsigned long long *snap_slots = nullptr;
+  RepAcc *snap_acc = nullptr;
+  // host staging
+  Control *h_ctl = nullptr;
+  unsigned long long *h_stat = nullptr;
+  hipStream_t stream = nullptr;
+  hipStream_t cap_stream = nullptr;
+  std::map<int, GraphEntry> graphs;
+  bool need_sort = true;
+  bool timing = false;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  double t_sum_ms = 0.0;
+  int64_t t_count = 0;
+  int chunk = 64;
+  int64_t steps_total = 0, sorts = 0, rollbacks = 0, list_builds = 0;
+  int64_t series_rows = 0;
+};
+
+namespace ptamd {
+
+static void sync(ptamd_system *s) { HIPCHK(hipStreamSynchronize(s->stream)); }
+
+static void h2d(ptamd_system *s, void *dst, const void *src, size_t bytes) {
+  HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s->stream));
+  sync(s);
+}
+
+static void d2h(ptamd_system *s, void *dst, const void *src, size_t bytes) {
+  HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s->stream));
+  sync(s);
+}
+
+static void d2d(ptamd_system *s, void *dst, const void *src, size_t bytes) {
+  HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s->stream));
+}
+
+static void check_launch() {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) fail(PTAMD_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+}
+
+static void invalidate_graphs(ptamd_system *s) {
+  for (auto &kv : s->graphs)
+    if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+  s->graphs.clear();
+}
+
+static void require_device(int *dev) {
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) fail(PTAMD_ENODEV, "no HIP device is visible");
+  HIPCHK(hipGetDevice(dev));
+  hipDeviceProp_t prop;
+  HIPCHK(hipGetDeviceProperties(&prop, *dev));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    fail(PTAMD_ENODEV, std::string("device is ") + prop.gcnArchName + ", this library is built for gfx950");
+}
+
+static void validate_sc(const ptamd_sc_params *sc) {
+  if (!sc) fail(PTAMD_EINVAL, "sc params are NULL");
+  auto integral = [](double v) { return v >= 1.0 && v <= 24.0 && std::floor(v) == v; };
+  if (!(sc->eps >= 0.0) || !(sc->a > 0.0) || !(sc->c >= 0.0)) fail(PTAMD_EINVAL, "need eps >= 0, a > 0, c >= 0");
+  if (!integral(sc->n) || !integral(sc->m)) fail(PTAMD_EINVAL, "exponents n and m must be integers in [1, 24]");
+  if (!(sc->rc > 0.0) || !(sc->rc <= 4.0 * sc->a)) fail(PTAMD_EINVAL, "need 0 < rc <= 4a");
+  if (sc->shift < 0 || sc->shift > 2) fail(PTAMD_EINVAL, "shift must be 0, 1 or 2");
+}
+
+static void validate_md(const ptamd_md_params *md) {
+  if (!md) fail(PTAMD_EINVAL, "md params are NULL");
+  if (!(md->dt_fs > 0.0) || !(md->dt_fs <= 10.0)) fail(PTAMD_EINVAL, "need 0 < dt <= 10 fs");
+  if (md->thermostat != 0 && md->thermostat != 1) fail(PTAMD_EINVAL, "thermostat must be 0 or 1");
+  if (md->thermostat && !(md->tau_fs > 0.0)) fail(PTAMD_EINVAL, "need tau > 0 with the thermostat");
+  if (md->precision != 0 && md->precision != 1) fail(PTAMD_EINVAL, "precision must be 0 (FP64) or 1 (mixed)");
+  if (!(md->skin > 0.0) || !(md->skin <= 3.0)) fail(PTAMD_EINVAL, "need 0 < skin <= 3 A");
+  const int l = md->lanes_per_atom;
+  if (!(l == 0 || l == 1 || l == 2 || l == 4 || l == 8 || l == 16))
+    fail(PTAMD_EINVAL, "lanes_per_atom must be 0 (auto), 1, 2, 4, 8 or 16");
+}
+
+// Shift constants of the chosen mode for f(r) = k (a/r)^p: f(rc) and f'(rc).
+static void shift_consts(const ptamd_sc_params &sc, double k, double pw, double *fc, double *dfc) {
+  const double v = k * std::pow(sc.a / sc.rc, pw);
+  *fc = (sc.shift >= 1) ? v : 0.0;
+  *dfc = (sc.shift == 2) ? -pw * v / sc.rc : 0.0;
+}
+
+static int auto_lpa(int64_t nreal) {
+  // enough lanes to keep ~4 waves per SIMD on 256 CUs (1024 SIMDs)
+  const double want = 4.0 * 1024.0 * 64.0 / (double)std::max<int64_t>(nreal, 1);
+  int l = 1;
+  while (l < 16 && l < want) l <<= 1;
+  return l;
+}
+
+static void alloc_buffers(Buffers &b, int64_t ntot, int precision, bool primary) {
+  b.x = dalloc<double>(ntot); b.y = dalloc<double>(ntot); b.z = dalloc<double>(ntot);
+  b.vx = dalloc<double>(ntot); b.vy = dalloc<double>(ntot); b.vz = dalloc<double>(ntot);
+  b.fx = dalloc<double>(ntot); b.fy = dalloc<double>(ntot); b.fz = dalloc<double>(ntot);
+  b.pos4 = precision ? (void *)dalloc<float4>(ntot) : (void *)dalloc<double4>(ntot);
+  b.group = dalloc<uint8_t>(ntot);
+  b.orig = dalloc<int32_t>(ntot);
+  b.cell = dalloc<int32_t>(ntot);
+  b.xs = dalloc<float>(ntot); b.ys = dalloc<float>(ntot); b.zs = dalloc<float>(ntot);
+  if (primary) {
+    b.xr = dalloc<float>(ntot); b.yr = dalloc<float>(ntot); b.zr = dalloc<float>(ntot);
+    b.ncount = dalloc<int32_t>(ntot);
+  }
+}
+
+static void free_buffers(Buffers &b) {
+  void *ptrs[] = {b.x, b.y, b.z, b.vx, b.vy, b.vz, b.fx, b.fy, b.fz, b.pos4, b.group, b.orig, b.cell,
+                  b.xs, b.ys, b.zs, b.xr, b.yr, b.zr, b.nbr, b.ncount, b.cell_start, b.cell_count,
+                  b.blk_rep, b.rep, b.acc, b.slots, b.stat, b.series, b.ctl};
+  for (void *p : ptrs) dfree(p);
+  b = Buffers{};
+}
+
+static void upload_reps(ptamd_system *s) {
+  std::vector<RepInfo> ri(s->n_rep);
+  for (int r = 0; r < s->n_rep; ++r) {
+    const RepHost &h = s->reps[r];
+    RepInfo &d = ri[r];
+    std::memset(&d, 0, sizeof(d));
+    d.abeg = h.abeg; d.aend = h.aend; d.nreal = h.nreal; d.nmob = h.nmob;
+    d.T0 = h.T0;
+    d.dof = 3.0 * (double)h.nmob - 3.0;
+    d.volume0 = h.volume0; d.area0 = h.area0; d.strain = h.strain;
+    for (int k = 0; k < 3; ++k) {
+      d.origin[k] = h.origin[k];
+      d.dims[k] = h.dims[k];
+      d.center[k] = h.center[k];
+    }
+    d.inv_h = h.inv_h;
+    d.cell_off = h.cell_off;
+    d.ncells = h.ncells;
+  }
+  h2d(s, s->B.rep, ri.data(), sizeof(RepInfo) * s->n_rep);
+}
+
+static void alloc_list(ptamd_system *s, int cap) {
+  cap = (cap + s->lpa - 1) / s->lpa * s->lpa;
+  dfree(s->B.nbr);
+  s->B.nbr = nullptr;
+  s->B.nbr = dalloc<int32_t>((size_t)s->ntot * cap);
+  s->cap = cap;
+  s->P.cap_slots = cap / s->lpa;
+  invalidate_graphs(s);
+}
+
+static void ensure_series(ptamd_system *s, int64_t rows) {
+  if (rows <= s->series_rows) return;
+  dfree(s->B.series);
+  s->B.series = nullptr;
+  s->B.series = dalloc<double>((size_t)s->n_rep * rows * kSeriesCols);
+  s->series_rows = rows;
+  s->B.series_cap = rows;
+  invalidate_graphs(s);
+}
+
+// ---------------------------------------------------------------------------
+// creation from per-replica host states
+// ---------------------------------------------------------------------------
+static ptamd_system *create_from_hosts(const std::vector<HostState> &hs, const std::vector<double> &T0,
+                                       const ptamd_sc_params &sc, const ptamd_md_params &md) {
+  auto *s = new ptamd_system();
+  try {
+    require_device(&s->device);
+    s->n_rep = (int)hs.size();
+    s->precision = md.precision;
+    s->sc = sc;
+    s->md = md;
+    s->skin = md.skin;
+    s->margin = 1.0;
+    s->bin_h = sc.rc + md.skin + 2.0 * s->margin;
+    HIPCHK(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
+    HIPCHK(hipEventCreate(&s->ev0));
+    HIPCHK(hipEventCreate(&s->ev1));
+    s->stream = nullptr;
+    // layout: each replica padded to whole tiles
+    int64_t off = 0, obase = 0;
+    s->reps.resize(s->n_rep);
+    for (int r = 0; r < s->n_rep; ++r) {
+      RepHost &h = s->reps[r];
+      const int64_t n = (int64_t)hs[r].x.size();
+      h.abeg = off;
+      h.nreal = n;
+      h.aend = off + (n + kTile - 1) / kTile * kTile;
+      h.orig_base = obase;
+      h.T0 = T0[r];
+      h.volume0 = hs[r].volume0;
+      h.area0 = hs[r].area0;
+      h.nmob = 0;
+      double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+      for (int64_t i = 0; i < n; ++i) {
+        h.nmob += hs[r].group[i] == 0;
+        const double c[3] = {hs[r].x[i], hs[r].y[i], hs[r].z[i]};
+        for (int k = 0; k < 3; ++k) {
+          if (!std::isfinite(c[k])) fail(PTAMD_EINVAL, "non-finite input position");
+          lo[k] = std::min(lo[k], c[k]);
+          hi[k] = std::max(hi[k], c[k]);
+        }
+      }
+      if (h.nmob < 2) fail(PTAMD_EINVAL, "a replica needs at least two mobile atoms");
+      for (int k = 0; k < 3; ++k) h.center[k] = 0.5 * (lo[k] + hi[k]);
+      off = h.aend;
+      obase += n;
+      s->nreal += n;
+    }
+    s->ntot = off;
+    if (s->ntot >= (int64_t)1 << 31) fail(PTAMD_EINVAL, "too many atoms for 32-bit indices");
+    s->lpa = md.lanes_per_atom ? md.lanes_per_atom : auto_lpa(s->nreal);
+
+    Params &P = s->P;
+    P.eps = sc.eps; P.a = sc.a; P.rc = sc.rc; P.rc2 = sc.rc * sc.rc; P.c_eps = sc.c * sc.eps;
+    P.n = (int32_t)sc.n; P.m = (int32_t)sc.m;
+    shift_consts(sc, sc.eps, sc.n, &P.Vc, &P.dVc);
+    shift_consts(sc, 1.0, sc.m, &P.rhoc, &P.drhoc);
+    const double rl = sc.rc + md.skin;
+    P.rlist2 = rl * rl;
+    P.half_skin2 = 0.25 * md.skin * md.skin;
+    P.margin2 = s->margin * s->margin;
+    P.esc2 = 1.0e8;  // 10^4 A around the cube centre
+    P.dt = md.dt_fs;
+    P.hdt_m = 0.5 * md.dt_fs / (kMassAl * kMvv2e);
+    P.tau = md.tau_fs;
+    P.thermostat = md.thermostat;
+    P.n_rep = s->n_rep;
+    P.mvv2e_m = kMassAl * kMvv2e;
+    P.kb = kBoltzmann;
+    P.gpa = kEvA3toGPa;
+    P.ntot = s->ntot;
+    P.lpa = s->lpa;
+    P.nbr_stride = s->ntot * s->lpa;
+
+    Buffers &B = s->B;
+    alloc_buffers(B, s->ntot, s->precision, true);
+    alloc_buffers(s->S, s->ntot, s->precision, false);
+    B.blk_rep = dalloc<int32_t>(s->ntot / kTile);
+    B.rep = dalloc<RepInfo>(s->n_rep);
+    B.acc = dalloc<RepAcc>(s->n_rep);
+    B.slots = dalloc<unsigned long long>((size_t)2 * s->n_rep * kSlots * kNQ);
+    B.stat = dalloc<unsigned long long>((size_t)s->n_rep * kSlots * 8);
+    B.ctl = dalloc<Control>(1);
+    s->d_key = dalloc<int32_t>(s->ntot);
+    s->d_tmp = dalloc<int32_t>(s->ntot);
+    s->d_perm = dalloc<int32_t>(s->ntot);
+    s->snap = dalloc<double>((size_t)9 * s->ntot);
+    s->snap_slots = dalloc<unsigned long long>((size_t)2 * s->n_rep * kSlots * kNQ);
+    s->snap_acc = dalloc<RepAcc>(s->n_rep);
+    HIPCHK(hipHostMalloc((void **)&s->h_ctl, sizeof(Control), 0));
+    HIPCHK(hipHostMalloc((void **)&s->h_stat, sizeof(unsigned long long) * s->n_rep * kSlots * 8, 0));
+
+    // list capacity: 1.3 x the lattice count within rc + skin, plus slack
+    const double dens = 4.0 / (sc.a * sc.a * sc.a);
+    const int cap0 = (int)(1.3 * dens * 4.18879 * rl * rl * rl) + 32;
+    alloc_list(s, cap0);
+    ensure_series(s, 1024);
+
+    // host arrays in padded layout
+    const int64_t N = s->ntot;
+    std::vector<double> hx(N, 0.0), hy(N, 0.0), hz(N, 0.0), hvx(N, 0.0), hvy(N, 0.0), hvz(N, 0.0);
+    std::vector<uint8_t> hg(N, kPad);
+    std::vector<int32_t> ho(N, -1);
+    s->blk_rep_h.assign(N / kTile, 0);
+    for (int r = 0; r < s->n_rep; ++r) {
+      const RepHost &h = s->reps[r];
+      for (int64_t t = h.abeg / kTile; t < h.aend / kTile; ++t) s->blk_rep_h[t] = r;
+      for (int64_t i = 0; i < h.nreal; ++i) {
+        const int64_t d = h.abeg + i;
+        hx[d] = hs[r].x[i]; hy[d] = hs[r].y[i]; hz[d] = hs[r].z[i];
+        hvx[d] = hs[r].vx[i]; hvy[d] = hs[r].vy[i]; hvz[d] = hs[r].vz[i];
+        hg[d] = hs[r].group[i];
+        ho[d] = (int32_t)(h.orig_base + i);
+      }
+      for (int64_t d = h.abeg + h.nreal; d < h.aend; ++d) {  // padding: parked at the centre, never used
+        hx[d] = h.center[0]; hy[d] = h.center[1]; hz[d] = h.center[2];
+      }
+    }
+    h2d(s, B.x, hx.data(), 8 * N); h2d(s, B.y, hy.data(), 8 * N); h2d(s, B.z, hz.data(), 8 * N);
+    h2d(s, B.vx, hvx.data(), 8 * N); h2d(s, B.vy, hvy.data(), 8 * N); h2d(s, B.vz, hvz.data(), 8 * N);
+    h2d(s, B.group, hg.data(), N);
+    h2d(s, B.orig, ho.data(), 4 * N);
+    h2d(s, B.blk_rep, s->blk_rep_h.data(), 4 * (N / kTile));
+    HIPCHK(hipMemsetAsync(B.fx, 0, 8 * N, s->stream));
+    HIPCHK(hipMemsetAsync(B.fy, 0, 8 * N, s->stream));
+    HIPCHK(hipMemsetAsync(B.fz, 0, 8 * N, s->stream));
+    Control c0{};
+    h2d(s, B.ctl, &c0, sizeof(Control));
+    upload_reps(s);
+    s->need_sort = true;
+    return s;
+  } catch (...) {
+    free_buffers(s->B);
+    free_buffers(s->S);
+    dfree(s->d_key); dfree(s->d_tmp); dfree(s->d_perm); dfree(s->d_cursor);
+    dfree(s->snap); dfree(s->snap_slots); dfree(s->snap_acc);
+    if (s->h_ctl) (void)hipHostFree(s->h_ctl);
+    if (s->h_stat) (void)hipHostFree(s->h_stat);
+    if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
+    if (s->ev0) (void)hipEventDestroy(s->ev0);
+    if (s->ev1) (void)hipEventDestroy(s->ev1);
+    delete s;
+    throw;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// spatial sort: bounding box -> grid -> counting sort -> per-cell order -> permute
+// ---------------------------------------------------------------------------
+static double okey_decode(unsigned long long u) {
+  const unsigned long long b = (u >> 63) ? (u & 0x7fffffffffffffffull) : ~u;
+  double d;
+  std::memcpy(&d, &b, 8);
+  return d;
+}
+
+static void sort_system(ptamd_system *s) {
+  Buffers &B = s->B;
+  const size_t nst = (size_t)s->n_rep * kSlots * 8;
+  std::vector<unsigned long long> init(nst);
+  for (size_t t = 0; t < nst; ++t) init[t] = ((t % 8) < 3) ? ~0ull : 0ull;
+  h2d(s, B.stat, init.data(), nst * 8);
+  launch_bbox(s->P, B, s->stream);
+  check_launch();
+  d2h(s, s->h_stat, B.stat, nst * 8);
+  int64_t cells = 0;
+  const double h = s->bin_h;
+  for (int r = 0; r < s->n_rep; ++r) {
+    RepHost &rh = s->reps[r];
+    unsigned long long mn[3] = {~0ull, ~0ull, ~0ull}, mx[3] = {0, 0, 0};
+    for (int sl = 0; sl < kSlots; ++sl)
+      for (int d = 0; d < 3; ++d) {
+        mn[d] = std::min(mn[d], s->h_stat[((size_t)r * kSlots + sl) * 8 + d]);
+        mx[d] = std::max(mx[d], s->h_stat[((size_t)r * kSlots + sl) * 8 + 3 + d]);
+      }
+    rh.inv_h = 1.0 / h;
+    int64_t nc = 1;
+    for (int d = 0; d < 3; ++d) {
+      const double lo = okey_decode(mn[d]), hi = okey_decode(mx[d]);
+      if (!std::isfinite(lo) || !std::isfinite(hi)) fail(PTAMD_ENONFINITE, "non-finite position at sort");
+      rh.origin[d] = lo - 0.5 * h;
+      const double span = std::floor((hi - rh.origin[d]) * rh.inv_h) + 1.0;
+      rh.dims[d] = (int)std::min<double>(std::max(span, 1.0), (double)kMaxDims);
+      nc *= rh.dims[d];
+    }
+    rh.cell_off = cells;
+    rh.ncells = nc + 1;  // + virtual cell for the padding
+    cells += rh.ncells;
+  }
+  if (cells > s->cells_cap) {
+    dfree(B.cell_start); dfree(B.cell_count); dfree(s->d_cursor);
+    B.cell_start = B.cell_count = s->d_cursor = nullptr;
+    const int64_t capc = cells + cells / 4 + 64;
+    B.cell_start = dalloc<int32_t>(capc);
+    B.cell_count = dalloc<int32_t>(capc + 2);
+    s->d_cursor = dalloc<int32_t>(capc);
+    s->cells_cap = capc;
+    invalidate_graphs(s);
+  }
+  upload_reps(s);
+  launch_fill_i64(reinterpret_cast<unsigned long long *>(B.cell_count), (cells + 1) / 2, 0ull, s->stream);
+  launch_assign_count(s->P, B, s->d_key, s->stream);
+  launch_scan_cells(s->P, B, s->d_cursor, s->stream);
+  launch_scatter(s->P, B, s->d_key, s->d_cursor, s->d_tmp, s->stream);
+  launch_cell_sort(s->P, B, s->d_tmp, s->d_perm, cells, s->stream);
+  launch_permute(s->P, B, s->S, s->d_perm, s->d_key, s->precision, s->stream);
+  check_launch();
+  const int64_t N = s->ntot;
+  d2d(s, B.x, s->S.x, 8 * N); d2d(s, B.y, s->S.y, 8 * N); d2d(s, B.z, s->S.z, 8 * N);
+  d2d(s, B.vx, s->S.vx, 8 * N); d2d(s, B.vy, s->S.vy, 8 * N); d2d(s, B.vz, s->S.vz, 8 * N);
+  d2d(s, B.fx, s->S.fx, 8 * N); d2d(s, B.fy, s->S.fy, 8 * N); d2d(s, B.fz, s->S.fz, 8 * N);
+  d2d(s, B.group, s->S.group, N);
+  d2d(s, B.orig, s->S.orig, 4 * N);
+  d2d(s, B.cell, s->S.cell, 4 * N);
+  d2d(s, B.xs, s->S.xs, 4 * N); d2d(s, B.ys, s->S.ys, 4 * N); d2d(s, B.zs, s->S.zs, 4 * N);
+  d2d(s, B.pos4, s->S.pos4, (s->precision ? 16 : 32) * N);
+  const int32_t one = 1;
+  HIPCHK(hipMemcpyAsync(&B.ctl->rebuild, &one, 4, hipMemcpyHostToDevice, s->stream));
+  sync(s);
+  s->need_sort = false;
+  s->sorts++;
+}
+
+// ---------------------------------------------------------------------------
+// MD steps
+// ---------------------------------------------------------------------------
+static GraphEntry &get_graph(ptamd_system *s, int K) {
+  auto it = s->graphs.find(K);
+  if (it != s->graphs.end()) return it->second;
+  GraphEntry g;
+  hipGraph_t graph;
+  HIPCHK(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
+  for (int32_t k = 0; k < K; ++k) {
+    launch_kick_drift(s->P, s->B, s->precision, k, 0, s->cap_stream);
+    launch_density(s->P, s->B, s->precision, s->lpa, k, s->cap_stream);
+    launch_force(s->P, s->B, s->precision, s->lpa, k, 0, s->cap_stream);
+  }
+  hipError_t e = hipStreamEndCapture(s->cap_stream, &graph);
+  if (e != hipSuccess) fail(PTAMD_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+  e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) fail(PTAMD_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+  return s->graphs[K] = g;
+}
+
+static void snapshot(ptamd_system *s, bool restore) {
+  const int64_t N = s->ntot;
+  double *arr[9] = {s->B.x, s->B.y, s->B.z, s->B.vx, s->B.vy, s->B.vz, s->B.fx, s->B.fy, s->B.fz};
+  const size_t nsl = (size_t)2 * s->n_rep * kSlots * kNQ * 8;
+  for (int k = 0; k < 9; ++k) {
+    if (restore) d2d(s, arr[k], s->snap + (size_t)k * N, 8 * N);
+    else d2d(s, s->snap + (size_t)k * N, arr[k], 8 * N);
+  }
+  if (restore) {
+    d2d(s, s->B.slots, s->snap_slots, nsl);
+    d2d(s, s->B.acc, s->snap_acc, sizeof(RepAcc) * s->n_rep);
+    launch_pos4(s->P, s->B, s->precision, s->stream);
+  } else {
+    d2d(s, s->snap_slots, s->B.slots, nsl);
+    d2d(s, s->snap_acc, s->B.acc, sizeof(RepAcc) * s->n_rep);
+  }
+}
+
+static void read_ctl(ptamd_system *s) { d2h(s, s->h_ctl, s->B.ctl, sizeof(Control)); }
+
+static void clear_err(ptamd_system *s) {
+  const int32_t z = 0;
+  HIPCHK(hipMemcpyAsync(&s->B.ctl->err, &z, 4, hipMemcpyHostToDevice, s->stream));
+  sync(s);
+}
+
+static void raise_err(int err) {
+  if (err & E_NONFINITE) fail(PTAMD_ENONFINITE, "a position, force or energy became non-finite");
+  if (err & E_ESCAPE) fail(PTAMD_EESCAPE, "an atom left the allowed region (1e4 A from the cube centre)");
+  if (err & E_STATE) fail(PTAMD_ESTATE, "thermostat met T <= 0 or lambda^2 < 0");
+}
+
+// initial forces of a burst (and of the force hook): density + force, forces only
+static void initial_forces(ptamd_system *s) {
+  if (s->need_sort) sort_system(s);
+  launch_burst_begin(s->P, s->B, s->n_rep, s->stream);
+  launch_set_base(s->B, 0, s->stream);
+  launch_density(s->P, s->B, s->precision, s->lpa, 0, s->stream);
+  launch_force(s->P, s->B, s->precision, s->lpa, 0, 1, s->stream);
+  check_launch();
+  read_ctl(s);
+  if (s->h_ctl->err & E_OVERFLOW) {
+    // grow the lists and try again from the same positions
+    alloc_list(s, s->cap * 3 / 2);
+    clear_err(s);
+    s->need_sort = true;
+    return initial_forces(s);
+  }
+  if (s->h_ctl->err & E_DRIFT) {
+    clear_err(s);
+    s->need_sort = true;
+    return initial_forces(s);
+  }
+  raise_err(s->h_ctl->err);
+}
+
+static void chunk_stats(ptamd_system *s, double *drift, double *vmax) {
+  const size_t nst = (size_t)s->n_rep * kSlots * 8;
+  launch_fill_i64(s->B.stat, (int64_t)nst, 0ull, s->stream);
+  launch_chunk_stats(s->P, s->B, s->stream);
+  check_launch();
+  HIPCHK(hipMemcpyAsync(s->h_stat, s->B.stat, nst * 8, hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(hipMemcpyAsync(s->h_ctl, s->B.ctl, sizeof(Control), hipMemcpyDeviceToHost, s->stream));
+  sync(s);
+  double d2 = 0.0, v2 = 0.0;
+  for (int r = 0; r < s->n_rep; ++r)
+    for (int sl = 0; sl < kSlots; ++sl) {
+      double a, b;
+      std::memcpy(&a, &s->h_stat[((size_t)r * kSlots + sl) * 4], 8);
+      std::memcpy(&b, &s->h_stat[((size_t)r * kSlots + sl) * 4 + 1], 8);
+      d2 = std::max(d2, a);
+      v2 = std::max(v2, b);
+    }
+  *drift = std::sqrt(d2);
+  *vmax = std::sqrt(v2);
+}
+
+static void run_burst(ptamd_system *s, int64_t n_steps, ptamd_averages *out) {
+  if (n_steps < 1) fail(PTAMD_EINVAL, "n_steps must be >= 1");
+  ensure_series(s, n_steps);
+  struct {
+    int64_t n, se;
+  } hdr{n_steps, n_steps >= kSEBlocks ? n_steps / kSEBlocks : 0};
+  h2d(s, &s->B.ctl->n_steps, &hdr, sizeof(hdr));
+  initial_forces(s);
+  double drift = 0.0, vmax = 0.0;
+  chunk_stats(s, &drift, &vmax);
+  int64_t step = 1;
+  int chunk = kStartChunk;  // the same schedule for every burst: results depend on the inputs only
+  while (step <= n_steps) {
+    // keep every atom within the binning margin of its sorted position until the next check
+    const double vb = std::max(vmax, 1e-4) * s->md.dt_fs * 1.5;
+    if (drift > 0.5 * s->margin) s->need_sort = true;
+    if (s->need_sort) {
+      sort_system(s);
+      drift = 0.0;
+    }
+    int K = (int)std::min<double>((0.8 * s->margin - drift) / vb, (double)kMaxChunk);
+    K = std::max(K, kMinChunk);
+    K = std::min<int64_t>(std::min(K, chunk), n_steps - step + 1);
+    snapshot(s, false);
+    launch_set_base(s->B, step, s->stream);
+    int done = 0;
+    if (s->timing) {
+      // the chunk's first step is launched directly, its force kernel bracketed
+      // by events on the system's stream; the rest of the chunk is a graph
+      launch_kick_drift(s->P, s->B, s->precision, 0, 0, s->stream);
+      launch_density(s->P, s->B, s->precision, s->lpa, 0, s->stream);
+      HIPCHK(hipEventRecord(s->ev0, s->stream));
+      launch_force(s->P, s->B, s->precision, s->lpa, 0, 0, s->stream);
+      HIPCHK(hipEventRecord(s->ev1, s->stream));
+      done = 1;
+      if (K > 1) launch_set_base(s->B, step + 1, s->stream);
+    }
+    check_launch();
+    if (K > done) HIPCHK(hipGraphLaunch(get_graph(s, K - done).exec, s->stream));
+    chunk_stats(s, &drift, &vmax);
+    const int err = s->h_ctl->err;
+    if (err & (E_DRIFT | E_OVERFLOW)) {
+      snapshot(s, true);
+      if (err & E_OVERFLOW) alloc_list(s, s->cap * 3 / 2);
+      clear_err(s);
+      s->need_sort = true;
+      s->rollbacks++;
+      chunk = std::max(kMinChunk, K / 2);
+      drift = 0.0;
+      if (s->rollbacks > 1000000) fail(PTAMD_EOVERFLOW, "too many roll-backs");
+      continue;
+    }
+    raise_err(err);
+    if (s->timing) {
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, s->ev0, s->ev1));
+      s->t_sum_ms += ms;
+      s->t_count++;
+    }
+    step += K;
+    s->steps_total += K;
+    chunk = std::min(kMaxChunk, chunk * 2);
+  }
+  s->chunk = std::max(kMinChunk, std::min(chunk, kMaxChunk));
+  // finalize: lambda of the last step, its sample, the averages
+  launch_set_base(s->B, n_steps + 1, s->stream);
+  launch_kick_drift(s->P, s->B, s->precision, 0, 1, s->stream);
+  check_launch();
+  std::vector<RepAcc> acc(s->n_rep);
+  HIPCHK(hipMemcpyAsync(acc.data(), s->B.acc, sizeof(RepAcc) * s->n_rep, hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(hipMemcpyAsync(s->h_ctl, s->B.ctl, sizeof(Control), hipMemcpyDeviceToHost, s->stream));
+  sync(s);
+  raise_err(s->h_ctl->err);
+  for (int r = 0; r < s->n_rep; ++r) {
+    const double *o = acc[r].out;
+    out[r].ke = o[0];
+    out[r].pe = o[1];
+    out[r].szz = o[2];
+    out[r].tz = o[3];
+    out[r].ke_se = o[4];
+    out[r].pe_se = o[5];
+    out[r].szz_se = o[6];
+    out[r].temp = o[7];
+    out[r].strain = o[8];
+    out[r].n_samples = (int64_t)o[9];
+  }
+}
+
+static void apply_strains(ptamd_system *s, const double *d_eps) {
+  std::vector<double> f(s->n_rep);
+  for (int r = 0; r < s->n_rep; ++r) {
+    if (!std::isfinite(d_eps[r]) || !(std::fabs(d_eps[r]) < 0.05)) fail(PTAMD_EINVAL, "need |d_eps| < 0.05");
+    const double e_new = s->reps[r].strain + d_eps[r];
+    if (!(1.0 + e_new > 0.0)) fail(PTAMD_EINVAL, "strain would invert the sample");
+  }
+  for (int r = 0; r < s->n_rep; ++r) {
+    const double e_old = s->reps[r].strain, e_new = e_old + d_eps[r];
+    f[r] = (1.0 + e_new) / (1.0 + e_old);
+    s->reps[r].strain = e_new;
+  }
+  double *df = dalloc<double>(s->n_rep);
+  try {
+    h2d(s, df, f.data(), 8 * s->n_rep);
+    launch_strain(s->P, s->B, df, s->stream);
+    launch_pos4(s->P, s->B, s->precision, s->stream);
+    check_launch();
+    sync(s);
+  } catch (...) {
+    dfree(df);
+    throw;
+  }
+  dfree(df);
+  upload_reps(s);
+  s->need_sort = true;
+}
+
+// state in/out in original order
+static void get_state(ptamd_system *s, double *x, double *y, double *z, double *vx, double *vy, double *vz) {
+  const int64_t N = s->ntot;
+  std::vector<double> t(N);
+  std::vector<int32_t> o(N);
+  d2h(s, o.data(), s->B.orig, 4 * N);
+  double *dst[6] = {x, y, z, vx, vy, vz};
+  double *src[6] = {s->B.x, s->B.y, s->B.z, s->B.vx, s->B.vy, s->B.vz};
+  for (int k = 0; k < 6; ++k) {
+    if (!dst[k]) continue;
+    d2h(s, t.data(), src[k], 8 * N);
+    for (int64_t i = 0; i < N; ++i)
+      if (o[i] >= 0) dst[k][o[i]] = t[i];
+  }
+}
+
+static void set_state(ptamd_system *s, const double *x, const double *y, const double *z, const double *vx,
+                      const double *vy, const double *vz) {
+  const int64_t N = s->ntot;
+  std::vector<int32_t> o(N);
+  std::vector<uint8_t> g(N);
+  d2h(s, o.data(), s->B.orig, 4 * N);
+  d2h(s, g.data(), s->B.group, N);
+  const double *src[6] = {x, y, z, vx, vy, vz};
+  for (int k = 0; k < 6; ++k) {
+    if (!src[k]) fail(PTAMD_EINVAL, "set_state needs all six arrays");
+    for (int64_t i = 0; i < s->nreal; ++i)
+      if (!std::isfinite(src[k][i])) fail(PTAMD_EINVAL, "non-finite value in set_state");
+  }
+  std::vector<double> t(N);
+  double *dst[6] = {s->B.x, s->B.y, s->B.z, s->B.vx, s->B.vy, s->B.vz};
+  std::vector<double> cur(N);
+  for (int k = 0; k < 6; ++k) {
+    d2h(s, cur.data(), dst[k], 8 * N);  // keeps the padding values
+    for (int64_t i = 0; i < N; ++i) {
+      if (o[i] < 0) continue;
+      double v = src[k][o[i]];
+      if (k >= 3 && g[i] != 0) v = 0.0;  // fixed atoms carry no velocity
+      cur[i] = v;
+    }
+    h2d(s, dst[k], cur.data(), 8 * N);
+  }
+  launch_pos4(s->P, s->B, s->precision, s->stream);
+  check_launch();
+  sync(s);
+  s->need_sort = true;
+}
+
+static void compute_forces(ptamd_system *s, double *fx, double *fy, double *fz, double *pe, double *wzz) {
+  initial_forces(s);
+  const int64_t N = s->ntot;
+  std::vector<int32_t> o(N);
+  std::vector<double> t(N);
+  d2h(s, o.data(), s->B.orig, 4 * N);
+  double *dst[3] = {fx, fy, fz};
+  double *src[3] = {s->B.fx, s->B.fy, s->B.fz};
+  for (int k = 0; k < 3; ++k) {
+    if (!dst[k]) continue;
+    d2h(s, t.data(), src[k], 8 * N);
+    for (int64_t i = 0; i < N; ++i)
+      if (o[i] >= 0) dst[k][o[i]] = t[i];
+  }
+  const size_t nsl = (size_t)s->n_rep * kSlots * kNQ;
+  std::vector<unsigned long long> sl(nsl);
+  d2h(s, sl.data(), s->B.slots, nsl * 8);  // parity 0
+  for (int r = 0; r < s->n_rep; ++r) {
+    long long q[kNQ] = {0};
+    for (int k = 0; k < kSlots; ++k)
+      for (int j = 0; j < kNQ; ++j) q[j] += (long long)sl[((size_t)r * kSlots + k) * kNQ + j];
+    if (pe) pe[r] = (double)(q[Q_EPAIR] + q[Q_EMB]) / kFix;
+    if (wzz) wzz[r] = (double)q[Q_WZZ] / kFix;
+  }
+}
+
+static void get_neighbors(ptamd_system *s, int64_t *offsets, int32_t *idx, int64_t cap, bool *overflow) {
+  s->need_sort = true;
+  initial_forces(s);  // sorts, rebuilds the lists at the current positions
+  const int64_t N = s->ntot;
+  std::vector<int32_t> o(N), cnt(N);
+  std::vector<int32_t> nb((size_t)N * s->cap);
+  d2h(s, o.data(), s->B.orig, 4 * N);
+  d2h(s, cnt.data(), s->B.ncount, 4 * N);
+  d2h(s, nb.data(), s->B.nbr, (size_t)4 * N * s->cap);
+  std::vector<std::vector<int32_t>> rows(s->nreal);
+  for (int64_t i = 0; i < N; ++i) {
+    if (o[i] < 0) continue;
+    auto &row = rows[o[i]];
+    row.reserve(cnt[i]);
+    for (int e = 0; e < cnt[i]; ++e) {
+      const int32_t j = nb[(size_t)(e / s->lpa) * s->P.nbr_stride + (size_t)i * s->lpa + (e % s->lpa)];
+      row.push_back(o[j]);
+    }
+    std::sort(row.begin(), row.end());
+  }
+  offsets[0] = 0;
+  *overflow = false;
+  for (int64_t a = 0; a < s->nreal; ++a) {
+    offsets[a + 1] = offsets[a] + (int64_t)rows[a].size();
+    for (size_t e = 0; e < rows[a].size(); ++e) {
+      const int64_t at = offsets[a] + (int64_t)e;
+      if (at < cap) idx[at] = rows[a][e];
+      else *overflow = true;
+    }
+  }
+}
+
+static void get_cells(ptamd_system *s, int32_t *cxyz, double *origin, double *inv_h, int32_t *dims) {
+  if (s->need_sort) sort_system(s);
+  const int64_t N = s->ntot;
+  std::vector<int32_t> o(N), c(N);
+  d2h(s, o.data(), s->B.orig, 4 * N);
+  d2h(s, c.data(), s->B.cell, 4 * N);
+  std::vector<int> rep_of(N);
+  for (int r = 0; r < s->n_rep; ++r)
+    for (int64_t i = s->reps[r].abeg; i < s->reps[r].aend; ++i) rep_of[i] = r;
+  for (int64_t i = 0; i < N; ++i) {
+    if (o[i] < 0) continue;
+    const RepHost &rh = s->reps[rep_of[i]];
+    const int cl = c[i];
+    cxyz[3 * (int64_t)o[i]] = cl % rh.dims[0];
+    cxyz[3 * (int64_t)o[i] + 1] = (cl / rh.dims[0]) % rh.dims[1];
+    cxyz[3 * (int64_t)o[i] + 2] = cl / (rh.dims[0] * rh.dims[1]);
+  }
+  for (int r = 0; r < s->n_rep; ++r) {
+    for (int d = 0; d < 3; ++d) {
+      if (origin) origin[3 * r + d] = s->reps[r].origin[d];
+      if (dims) dims[3 * r + d] = s->reps[r].dims[d];
+    }
+    if (inv_h) inv_h[r] = s->reps[r].inv_h;
+  }
+}
+
+static void count_pairs(ptamd_system *s, int64_t *pairs, int64_t *entries) {
+  if (s->need_sort) initial_forces(s);
+  const size_t nst = (size_t)s->n_rep * kSlots * 8;
+  launch_fill_i64(s->B.stat, (int64_t)nst, 0ull, s->stream);
+  launch_count_pairs(s->P, s->B, s->precision, s->stream);
+  check_launch();
+  d2h(s, s->h_stat, s->B.stat, nst * 8);
+  unsigned long long p = 0, e = 0;
+  for (int r = 0; r < s->n_rep; ++r)
+    for (int sl = 0; sl < kSlots; ++sl) {
+      p += s->h_stat[((size_t)r * kSlots + sl) * 4];
+      e += s->h_stat[((size_t)r * kSlots + sl) * 4 + 1];
+    }
+  *pairs = (int64_t)(p / 2);
+  *entries = (int64_t)e;
+}
+
+static void destroy(ptamd_system *s) {
+  if (!s) return;
+  if (s->stream) (void)hipStreamSynchronize(s->stream);
+  else (void)hipDeviceSynchronize();
+  invalidate_graphs(s);
+  free_buffers(s->B);
+  free_buffers(s->S);
+  dfree(s->d_key); dfree(s->d_tmp); dfree(s->d_perm); dfree(s->d_cursor);
+  dfree(s->snap); dfree(s->snap_slots); dfree(s->snap_acc);
+  if (s->h_ctl) (void)hipHostFree(s->h_ctl);
+  if (s->h_stat) (void)hipHostFree(s->h_stat);
+  if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
+  if (s->ev0) (void)hipEventDestroy(s->ev0);
+  if (s->ev1) (void)hipEventDestroy(s->ev1);
+  delete s;
+}
+
+template <class F> static ptamd_status guard(F &&f) {
+  try {
+    f();
+    return PTAMD_OK;
+  } catch (const Failure &e) {
+    g_last_error = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    g_last_error = "host allocation failed";
+    return PTAMD_ENOMEM;
+  } catch (const std::exception &e) {
+    g_last_error = e.what();
+    return PTAMD_EDEVICE;
+  }
+}
+
+static void use_device(const ptamd_system *s) {
+  if (!s) fail(PTAMD_EINVAL, "system handle is NULL");
+  HIPCHK(hipSetDevice(s->device));
+}
+
+}  // namespace ptamd
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char *ptamd_last_error(void) { return g_last_error.c_str(); }
+
+const char *ptamd_version(void) { return "ptamd 0.1 (gfx950)"; }
+
+static void validate_desc(const ptamd_lattice_desc *d) {
+  if (!d) fail(PTAMD_EINVAL, "lattice desc is NULL");
+  if (d->fix_slabs ? d->n_cells < 4 : d->n_cells < 1)
+    fail(PTAMD_EINVAL, "need n_cells >= 4 with fixed regions (>= 1 without)");
+  if (d->n_cells > 400) fail(PTAMD_EINVAL, "n_cells > 400");
+  if (!(d->lattice_a > 0.0) || !(d->T0 >= 0.0)) fail(PTAMD_EINVAL, "need lattice_a > 0 and T0 >= 0");
+}
+
+ptamd_status ptamd_create_system(const ptamd_lattice_desc *desc, const ptamd_sc_params *sc,
+                                 const ptamd_md_params *md, ptamd_system **out) {
+  return ptamd_create_batch(1, desc, sc, md, out);
+}
+
+ptamd_status ptamd_create_batch(int32_t n_replicas, const ptamd_lattice_desc *descs, const ptamd_sc_params *sc,
+                                const ptamd_md_params *md, ptamd_system **out) {
+  return guard([&] {
+    if (!out) fail(PTAMD_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n_replicas < 1 || n_replicas > 4096) fail(PTAMD_EINVAL, "need 1 <= n_replicas <= 4096");
+    if (!descs) fail(PTAMD_EINVAL, "descs is NULL");
+    validate_sc(sc);
+    validate_md(md);
+    std::vector<HostState> hs(n_replicas);
+    std::vector<double> T0(n_replicas);
+    for (int r = 0; r < n_replicas; ++r) {
+      validate_desc(&descs[r]);
+      build_cube(descs[r].n_cells, descs[r].lattice_a, descs[r].fix_slabs != 0, descs[r].T0, descs[r].seed, hs[r]);
+      T0[r] = descs[r].T0;
+    }
+    *out = create_from_hosts(hs, T0, *sc, *md);
+  });
+}
+
+ptamd_status ptamd_create_system_from_state(int64_t n, const double *x, const double *y, const double *z,
+                                            const double *vx, const double *vy, const double *vz,
+                                            const uint8_t *group, double volume0, double area0, double T0,
+                                            const ptamd_sc_params *sc, const ptamd_md_params *md,
+                                            ptamd_system **out) {
+  return guard([&] {
+    if (!out) fail(PTAMD_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n < 2 || n > (int64_t)1 << 30) fail(PTAMD_EINVAL, "need 2 <= n <= 2^30");
+    if (!x || !y || !z || !vx || !vy || !vz || !group) fail(PTAMD_EINVAL, "NULL array");
+    if (!(volume0 > 0.0) || !(area0 >= 0.0) || !(T0 >= 0.0)) fail(PTAMD_EINVAL, "need volume0 > 0, area0 >= 0, T0 >= 0");
+    validate_sc(sc);
+    validate_md(md);
+    std::vector<HostState> hs(1);
+    HostState &h = hs[0];
+    h.x.assign(x, x + n); h.y.assign(y, y + n); h.z.assign(z, z + n);
+    h.vx.assign(vx, vx + n); h.vy.assign(vy, vy + n); h.vz.assign(vz, vz + n);
+    h.group.assign(group, group + n);
+    for (int64_t i = 0; i < n; ++i) {
+      if (h.group[i] > 2) fail(PTAMD_EINVAL, "group values must be 0, 1 or 2");
+      if (!std::isfinite(vx[i]) || !std::isfinite(vy[i]) || !std::isfinite(vz[i]))
+        fail(PTAMD_EINVAL, "non-finite input velocity");
+      if (h.group[i] != 0) h.vx[i] = h.vy[i] = h.vz[i] = 0.0;
+    }
+    h.volume0 = volume0;
+    h.area0 = area0;
+    *out = create_from_hosts(hs, std::vector<double>{T0}, *sc, *md);
+  });
+}
+
+ptamd_status ptamd_destroy_system(ptamd_system *sys) {
+  return guard([&] {
+    if (!sys) return;
+    (void)hipSetDevice(sys->device);
+    destroy(sys);
+  });
+}
+
+ptamd_status ptamd_apply_strain_increment(ptamd_system *sys, double d_eps) {
+  return guard([&] {
+    use_device(sys);
+    std::vector<double> d(sys->n_rep, d_eps);
+    apply_strains(sys, d.data());
+  });
+}
+
+ptamd_status ptamd_apply_strain_increments(ptamd_system *sys, const double *d_eps) {
+  return guard([&] {
+    use_device(sys);
+    if (!d_eps) fail(PTAMD_EINVAL, "d_eps is NULL");
+    apply_strains(sys, d_eps);
+  });
+}
+
+ptamd_status ptamd_run_fast_md(ptamd_system *sys, int64_t n_steps, ptamd_averages *out) {
+  return guard([&] {
+    use_device(sys);
+    if (!out) fail(PTAMD_EINVAL, "out is NULL");
+    run_burst(sys, n_steps, out);
+  });
+}
+
+ptamd_status ptamd_get_num_atoms(const ptamd_system *sys, int64_t *n) {
+  return guard([&] {
+    if (!sys || !n) fail(PTAMD_EINVAL, "NULL argument");
+    *n = sys->nreal;
+  });
+}
+
+ptamd_status ptamd_get_state(ptamd_system *sys, double *x, double *y, double *z, double *vx, double *vy,
+                             double *vz) {
+  return guard([&] {
+    use_device(sys);
+    get_state(sys, x, y, z, vx, vy, vz);
+  });
+}
+
+ptamd_status ptamd_set_state(ptamd_system *sys, const double *x, const double *y, const double *z,
+                             const double *vx, const double *vy, const double *vz) {
+  return guard([&] {
+    use_device(sys);
+    set_state(sys, x, y, z, vx, vy, vz);
+  });
+}
+
+ptamd_status ptamd_get_strain(const ptamd_system *sys, double *strain) {
+  return guard([&] {
+    if (!sys || !strain) fail(PTAMD_EINVAL, "NULL argument");
+    for (int r = 0; r < sys->n_rep; ++r) strain[r] = sys->reps[r].strain;
+  });
+}
+
+ptamd_status ptamd_compute_forces(ptamd_system *sys, double *fx, double *fy, double *fz, double *pe, double *wzz) {
+  return guard([&] {
+    use_device(sys);
+    compute_forces(sys, fx, fy, fz, pe, wzz);
+  });
+}
+
+ptamd_status ptamd_get_neighbors(ptamd_system *sys, int64_t *offsets, int32_t *idx, int64_t cap) {
+  ptamd_status st = PTAMD_OK;
+  ptamd_status g = guard([&] {
+    use_device(sys);
+    if (!offsets) fail(PTAMD_EINVAL, "offsets is NULL");
+    if (cap > 0 && !idx) fail(PTAMD_EINVAL, "idx is NULL");
+    bool of = false;
+    get_neighbors(sys, offsets, idx, cap, &of);
+    if (of) {
+      g_last_error = "idx capacity too small; offsets hold the required size";
+      st = PTAMD_EOVERFLOW;
+    }
+  });
+  return g != PTAMD_OK ? g : st;
+}
+
+ptamd_status ptamd_get_cells(ptamd_system *sys, int32_t *cxyz, double *origin, double *inv_h, int32_t *dims) {
+  return guard([&] {
+    use_device(sys);
+    if (!cxyz) fail(PTAMD_EINVAL, "cxyz is NULL");
+    get_cells(sys, cxyz, origin, inv_h, dims);
+  });
+}
+
+ptamd_status ptamd_get_series(ptamd_system *sys, int32_t replica, double *buf, int64_t cap) {
+  return guard([&] {
+    use_device(sys);
+    if (replica < 0 || replica >= sys->n_rep) fail(PTAMD_EINVAL, "replica out of range");
+    if (!buf || cap < 0) fail(PTAMD_EINVAL, "bad buffer");
+    const int64_t rows = std::min(cap, sys->series_rows);
+    if (rows > 0)
+      d2h(sys, buf, sys->B.series + (size_t)replica * sys->series_rows * kSeriesCols,
+          (size_t)rows * kSeriesCols * 8);
+  });
+}
+
+ptamd_status ptamd_get_info(const ptamd_system *sys, ptamd_info *info) {
+  return guard([&] {
+    if (!sys || !info) fail(PTAMD_EINVAL, "NULL argument");
+    info->n_atoms = sys->nreal;
+    info->n_replicas = sys->n_rep;
+    info->precision = sys->precision;
+    info->lanes_per_atom = sys->lpa;
+    info->list_capacity = sys->cap;
+    info->list_builds = sys->h_ctl ? sys->h_ctl->list_builds : 0;
+    info->sorts = sys->sorts;
+    info->rollbacks = sys->rollbacks;
+    info->steps = sys->steps_total;
+    info->skin = sys->skin;
+    info->bin_margin = sys->margin;
+  });
+}
+
+ptamd_status ptamd_set_stream(ptamd_system *sys, void *hip_stream) {
+  return guard([&] {
+    use_device(sys);
+    HIPCHK(hipStreamSynchronize(sys->stream));
+    sys->stream = static_cast<hipStream_t>(hip_stream);
+  });
+}
+
+ptamd_status ptamd_kernel_timing(ptamd_system *sys, double *avg_ms, int64_t *count, int32_t reset) {
+  return guard([&] {
+    if (!sys) fail(PTAMD_EINVAL, "NULL system");
+    sys->timing = true;
+    if (avg_ms) *avg_ms = sys->t_count ? sys->t_sum_ms / (double)sys->t_count : 0.0;
+    if (count) *count = sys->t_count;
+    if (reset) {
+      sys->t_sum_ms = 0.0;
+      sys->t_count = 0;
+    }
+  });
+}
+
+ptamd_status ptamd_count_pairs(ptamd_system *sys, int64_t *pairs_in_rc, int64_t *list_entries) {
+  return guard([&] {
+    use_device(sys);
+    if (!pairs_in_rc || !list_entries) fail(PTAMD_EINVAL, "NULL argument");
+    count_pairs(sys, pairs_in_rc, list_entries);
+  });
+}
+
+}  // extern "C"

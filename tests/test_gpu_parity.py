@@ -1,0 +1,313 @@
+"""GPU path (through the C ABI) against the FP64 oracle on the same seeded
+inputs.
+
+Bars (written here, per result):
+  - lists and cells: bit-exact (integer results decided in FP64 on both sides
+    with the same formula and no contraction);
+  - FP64 path: per-atom force |dF| <= 1e-5 max(|F_ref|, F_rms_ref); energy
+    |dU|/N <= 1e-6 eV; trajectories of up to 100 steps: |dr| <= 1e-8 A,
+    |dv| <= 1e-10 A/fs; burst averages to the same relative 1e-9;
+  - mixed path (FP32 pair and density terms): per-atom force 2e-4 relative to
+    max(|F|, F_rms), energy 1e-5 eV/atom, 100-step |dr| <= 1e-4 A; the
+    measured errors are printed.
+"""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_2603_07321_amd")
+
+
+def _orc():
+    import oracle
+    return oracle
+
+
+def _state(nc, noise, T, seed, fix=True):
+    O = _orc()
+    s = synth.cube_state(nc, noise, 0.0, seed, fix_slabs=fix)
+    vx, vy, vz = O.mb_velocities(s["group"], T, seed)
+    s.update(vx=vx, vy=vy, vz=vz)
+    return s
+
+
+def _gpu_from(s, T0=300.0, precision=0, lpa=0, thermostat=1, sc=None, skin=1.0):
+    md = P.md_params(precision=precision, lanes_per_atom=lpa, thermostat=thermostat, skin=skin)
+    return P.System.from_state(s, T0=T0, sc=sc or P.sc_params(), md=md)
+
+
+def _orc_state(s):
+    O = _orc()
+    return O.State(s["x"].copy(), s["y"].copy(), s["z"].copy(), s["vx"].copy(), s["vy"].copy(), s["vz"].copy(),
+                   s["group"].copy(), s["volume0"], s["area0"])
+
+
+def _force_err(g, ref):
+    F = np.stack([ref["fx"], ref["fy"], ref["fz"]], 1)
+    G = np.stack([g["fx"], g["fy"], g["fz"]], 1)
+    frms = np.sqrt((F ** 2).sum(1).mean())
+    den = np.maximum(np.linalg.norm(F, axis=1), frms)
+    return (np.linalg.norm(G - F, axis=1) / den).max()
+
+
+# --------------------------------------------------------------------------
+# a1: lattice and Maxwell-Boltzmann initial state
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("nc,T0,seed", [(4, 300.0, 1), (7, 123.0, 99)])
+def test_create_system_matches_oracle(nc, T0, seed):
+    O = _orc()
+    with P.System.cube(nc, T0=T0, seed=seed) as s:
+        st = s.get_state()
+    x, y, z, g, _ = O.fcc_cube(nc, 4.05, True)
+    assert np.array_equal(st["x"], x) and np.array_equal(st["y"], y) and np.array_equal(st["z"], z)
+    vx, vy, vz = O.mb_velocities(g, T0, seed)
+    for a, b in ((st["vx"], vx), (st["vy"], vy), (st["vz"], vz)):
+        assert np.abs(a - b).max() <= 1e-14 * np.abs(b).max()
+
+
+# --------------------------------------------------------------------------
+# a3: cells and Verlet lists, bit-exact
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("case", ["perfect", "thermal", "strained", "gas", "ragged"])
+def test_cells_and_lists_bit_exact(case):
+    O = _orc()
+    if case == "perfect":
+        s = synth.cube_state(6, 0.0, 0.0, 1)
+    elif case == "thermal":
+        s = synth.cube_state(7, 0.15, 0.0, 2)
+    elif case == "gas":
+        x, y, z = synth.gas(5, 7.0, 3, jitter=1.0)
+        s = dict(x=x, y=y, z=z, group=np.zeros(len(x), np.uint8), volume0=1e5, area0=0.0)
+    elif case == "ragged":
+        s = synth.cube_state(5, 0.1, 0.0, 4)
+        keep = np.arange(len(s["x"])) % 7 != 3  # 429 atoms removed: N not a tile multiple
+        s = {k: (v[keep] if isinstance(v, np.ndarray) else v) for k, v in s.items()}
+    else:
+        s = synth.cube_state(6, 0.1, 0.0, 5)
+    n = len(s["x"])
+    for k in ("vx", "vy", "vz"):
+        s[k] = np.zeros(n)
+    with _gpu_from(s, precision=1, lpa=4) as g:
+        if case == "strained":
+            g.apply_strain_increment(1e-4)
+            g.apply_strain_increment(-3e-4)
+        st = g.get_state()
+        off, idx = g.get_neighbors()
+        cxyz, origin, inv_h, dims = g.get_cells()
+    roff, ridx = O.neighbors(st["x"], st["y"], st["z"], 8.1 + 1.0)
+    assert np.array_equal(off, roff)
+    assert np.array_equal(idx, ridx)
+    rc = O.cell_assign(st["x"], st["y"], st["z"], origin[0], inv_h[0], dims[0])
+    assert np.array_equal(cxyz, rc)
+
+
+# --------------------------------------------------------------------------
+# a4-a5: density, forces, energy, virial
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("precision,lpa", [(0, 1), (0, 4), (0, 16), (1, 1), (1, 8)])
+@pytest.mark.parametrize("shift", [2, 1])
+def test_forces_energy_virial(precision, lpa, shift):
+    O = _orc()
+    s = _state(6, 0.12, 300.0, 11)
+    scp = P.sc_params(shift=shift, rc=8.1 if shift == 2 else 7.9)
+    with _gpu_from(s, precision=precision, lpa=lpa, sc=scp) as g:
+        f = g.compute_forces()
+    ref = O.forces(s["x"], s["y"], s["z"], O.sc_params(shift=shift, rc=8.1 if shift == 2 else 7.9), s["group"])
+    n = len(s["x"])
+    ferr = _force_err(f, ref)
+    uerr = abs(f["U"][0] - ref["U"]) / n
+    werr = abs(f["Wzz"][0] - ref["Wzz"]) / max(abs(ref["Wzz"]), 1.0)
+    print(f"\nprecision={precision} lpa={lpa} shift={shift}: force {ferr:.2e} U/atom {uerr:.2e} W {werr:.2e}")
+    if precision == 0:
+        assert ferr <= 1e-5 and uerr <= 1e-6 and werr <= 1e-8
+    else:
+        assert ferr <= 2e-4 and uerr <= 1e-5 and werr <= 1e-4
+
+
+def test_forces_free_cluster_newton():
+    O = _orc()
+    s = _state(3, 0.2, 300.0, 12, fix=False)
+    with _gpu_from(s, precision=0, lpa=2) as g:
+        f = g.compute_forces()
+    ref = O.forces(s["x"], s["y"], s["z"], O.sc_params(), s["group"])
+    assert _force_err(f, ref) <= 1e-5
+    assert abs(f["fx"].sum()) < 1e-10 and abs(f["fz"].sum()) < 1e-10
+
+
+# --------------------------------------------------------------------------
+# a6-a9: trajectories and burst averages
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("n_steps", [1, 10, 100])
+@pytest.mark.parametrize("thermostat", [1, 0])
+def test_trajectory_fp64(n_steps, thermostat):
+    O = _orc()
+    s = _state(5, 0.05, 300.0, 21)
+    with _gpu_from(s, precision=0, lpa=4, thermostat=thermostat) as g:
+        avg = g.run_fast_md(n_steps)[0]
+        st = g.get_state()
+        ser = g.get_series(0, n_steps)
+    os_ = _orc_state(s)
+    ravg, rser = O.run_burst(os_, O.sc_params(), O.md_params(thermostat=thermostat), n_steps, series=True)
+    dr = max(np.abs(st[k] - getattr(os_, k)).max() for k in ("x", "y", "z"))
+    dv = max(np.abs(st[k] - getattr(os_, k)).max() for k in ("vx", "vy", "vz"))
+    print(f"\nFP64 n={n_steps} thermo={thermostat}: |dr| {dr:.2e} |dv| {dv:.2e}")
+    assert dr <= 1e-8 and dv <= 1e-10
+    for k in ("ke", "pe", "szz", "tz"):
+        assert avg[k] == pytest.approx(ravg[k], rel=1e-9, abs=1e-9), k
+    assert avg["n_samples"] == n_steps
+    assert np.allclose(ser[:, :3], rser[:, :3], rtol=1e-9, atol=1e-9)
+    assert np.allclose(ser[:, 3:6], rser[:, 3:6], rtol=1e-9, atol=1e-9)
+    if n_steps >= 20:
+        for k in ("ke_se", "pe_se", "szz_se"):
+            assert avg[k] == pytest.approx(ravg[k], rel=1e-6, abs=1e-9)
+    else:
+        assert np.isnan(avg["ke_se"])
+
+
+def test_trajectory_mixed_error_stated():
+    O = _orc()
+    s = _state(5, 0.05, 300.0, 22)
+    with _gpu_from(s, precision=1, lpa=8) as g:
+        avg = g.run_fast_md(100)[0]
+        st = g.get_state()
+    os_ = _orc_state(s)
+    ravg, _ = O.run_burst(os_, O.sc_params(), O.md_params(), 100)
+    dr = max(np.abs(st[k] - getattr(os_, k)).max() for k in ("x", "y", "z"))
+    print(f"\nmixed 100 steps: |dr| {dr:.2e}, dKE {avg['ke'] - ravg['ke']:.2e}, dPE {avg['pe'] - ravg['pe']:.2e}, "
+          f"dszz {avg['szz'] - ravg['szz']:.2e}")
+    assert dr <= 1e-4
+    assert abs(avg["pe"] - ravg["pe"]) / len(s["x"]) <= 1e-5
+
+
+def test_strain_then_burst_matches_oracle():
+    O = _orc()
+    s = _state(5, 0.05, 300.0, 23)
+    with _gpu_from(s, precision=0, lpa=2) as g:
+        g.apply_strain_increment(1e-4)
+        avg1 = g.run_fast_md(30)[0]
+        g.apply_strain_increment(-1e-4)
+        avg2 = g.run_fast_md(30)[0]
+        st = g.get_state()
+        strain = g.strain()[0]
+    os_ = _orc_state(s)
+    O.apply_strain(os_, 1e-4)
+    r1, _ = O.run_burst(os_, O.sc_params(), O.md_params(), 30)
+    O.apply_strain(os_, -1e-4)
+    r2, _ = O.run_burst(os_, O.sc_params(), O.md_params(), 30)
+    assert strain == pytest.approx(0.0, abs=1e-18)
+    assert np.abs(st["z"] - os_.z).max() <= 1e-8
+    for a, b in ((avg1, r1), (avg2, r2)):
+        for k in ("ke", "pe", "szz", "tz"):
+            assert a[k] == pytest.approx(b[k], rel=1e-9, abs=1e-9)
+
+
+def test_gas_thermostat_closed_form():
+    """No interactions: T_n - T0 = (1 - dt/tau)^n (T_init - T0)."""
+    O = _orc()
+    x, y, z = synth.gas(6, 20.0, 1)
+    g0 = np.zeros(len(x), np.uint8)
+    vx, vy, vz = O.mb_velocities(g0, 450.0, 3)
+    s = dict(x=x, y=y, z=z, vx=vx, vy=vy, vz=vz, group=g0, volume0=1e6, area0=0.0)
+    with _gpu_from(s, T0=300.0, precision=0) as g:
+        g.run_fast_md(300)
+        ser = g.get_series(0, 300)
+    k = np.arange(1, 301)
+    assert np.allclose(ser[:, 3], 300.0 + 0.99 ** k * 150.0, rtol=1e-10)
+    assert np.all(ser[:, 1] == 0.0)
+
+
+# --------------------------------------------------------------------------
+# determinism, batching, edge cases
+# --------------------------------------------------------------------------
+def test_run_twice_bitwise_equal():
+    outs = []
+    for _ in range(2):
+        with P.System.cube(8, md=P.md_params(precision=1)) as g:
+            a = g.run_fast_md(150)[0]
+            st = g.get_state()
+        outs.append((a, st))
+    assert outs[0][0] == outs[1][0]
+    for k in outs[0][1]:
+        assert np.array_equal(outs[0][1][k], outs[1][1][k])
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_equals_individual(precision):
+    """Replicas in one batch follow the same trajectories as alone.  The batch
+    shares list rebuilds and re-sorts between replicas, which changes the
+    order of per-atom sums, so agreement is to rounding, not bitwise."""
+    descs = [P.lattice_desc(5, 200.0, 3), P.lattice_desc(7, 400.0, 4), P.lattice_desc(4, 300.0, 5)]
+    md = P.md_params(precision=precision, lanes_per_atom=4)
+    with P.System.batch(descs, md=md) as b:
+        b.apply_strain_increments([1e-4, -1e-4, 0.0])
+        avg_b = b.run_fast_md(60)
+        st_b = b.get_state()
+    off = 0
+    for r, d in enumerate(descs):
+        with P.System(P.create_system(d, P.sc_params(), md)) as s:
+            s.apply_strain_increment([1e-4, -1e-4, 0.0][r])
+            a = s.run_fast_md(60)[0]
+            st = s.get_state()
+        n = len(st["x"])
+        # FP32 pair sums in another order round differently (~1e-7 relative
+        # per force); over 60 steps that reaches ~1e-8 in the averages
+        rel, dxm = (1e-9, 1e-8) if precision == 0 else (1e-6, 1e-6)
+        for k in ("ke", "pe", "szz", "tz"):
+            assert a[k] == pytest.approx(avg_b[r][k], rel=rel, abs=rel)
+        for k in st:
+            assert np.abs(st[k] - st_b[k][off:off + n]).max() <= dxm
+        off += n
+
+
+def test_lanes_per_atom_do_not_change_results_beyond_rounding():
+    s = _state(6, 0.1, 300.0, 31)
+    res = []
+    for lpa in (1, 2, 8):
+        with _gpu_from(s, precision=0, lpa=lpa) as g:
+            res.append(g.run_fast_md(40)[0])
+    for r in res[1:]:
+        for k in ("ke", "pe", "szz"):
+            assert r[k] == pytest.approx(res[0][k], rel=1e-10, abs=1e-10)
+
+
+def test_set_state_roundtrip_and_rollback():
+    with P.System.cube(6, md=P.md_params(precision=1)) as g:
+        st0 = g.get_state()
+        a1 = g.run_fast_md(50)[0]
+        g.set_state(st0)
+        a2 = g.run_fast_md(50)[0]
+    assert a1 == a2
+
+
+def test_far_escaped_atom_is_handled():
+    """An atom 300 A away (clamped into the edge cells of the binning grid)."""
+    O = _orc()
+    s = _state(5, 0.05, 300.0, 41)
+    s["x"] = s["x"].copy()
+    mob = np.where(s["group"] == 0)[0]
+    s["x"][mob[:3]] += 300.0
+    with _gpu_from(s, precision=0, lpa=2) as g:
+        avg = g.run_fast_md(20)[0]
+    os_ = _orc_state(s)
+    ravg, _ = O.run_burst(os_, O.sc_params(), O.md_params(), 20)
+    assert avg["pe"] == pytest.approx(ravg["pe"], rel=1e-9)
+
+
+def test_nonfinite_input_rejected():
+    s = _state(4, 0.0, 300.0, 1)
+    s["vx"] = s["vx"].copy()
+    s["vx"][np.where(s["group"] == 0)[0][0]] = np.nan
+    with pytest.raises(P.PtamdError) as ei:
+        _gpu_from(s)
+    assert ei.value.name == "PTAMD_EINVAL"
+
+
+def test_invalid_run_arguments():
+    with P.System.cube(4) as g:
+        with pytest.raises(P.PtamdError):
+            g.run_fast_md(0)
+        with pytest.raises(P.PtamdError):
+            g.apply_strain_increment(0.5)
