@@ -44,7 +44,12 @@ def main() -> int:
     ap.add_argument("--cells", type=int, default=25)
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tune-steps", type=int, default=100)
     ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="before the timed region, copy this many MiB device-to-device (a known-size kernel "
+                         "for scaling hardware byte counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -68,6 +73,17 @@ def main() -> int:
     stream = torch.cuda.current_stream()
     sysm.set_stream(stream)
     n_atoms = sysm.n_atoms()
+    if args.copy_probe_mb > 0:
+        nb = args.copy_probe_mb * (1 << 20) // 4
+        src = torch.ones(nb, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    tune = None
+    if not args.no_autotune:
+        # warm-up work: probe bursts pick lanes per atom and skin, state restored
+        tune = sysm.autotune(probe_steps=args.tune_steps)
     sysm.kernel_timing(reset=True)  # switches on the force-kernel events
 
     for _ in range(args.warmup):
@@ -132,6 +148,8 @@ def main() -> int:
             "burst_steps": args.burst,
             "precision": "mixed" if args.precision == 1 else "fp64",
             "lanes_per_atom": info1["lanes_per_atom"],
+            "skin_A": info1["skin"],
+            "autotune": tune,
         },
         "hbm_frac_algorithmic": hbm_algo / HBM_PEAK_GBS,
         "roofline": roofline,

@@ -86,7 +86,8 @@ typedef struct {
 /* precision: 0 = FP64 everywhere; 1 = mixed (pair and density terms in FP32;
  * state, forces-to-velocity update and all global sums in FP64 / 64-bit fixed
  * point).  skin: Verlet-list skin in A (0 < skin <= 3).  lanes_per_atom:
- * 0 = autotune, else one of 1, 2, 4, 8, 16.  thermostat: 0 = NVE,
+ * lanes of a wavefront that share one atom's pair sums; 0 = chosen from the
+ * atom count (ptamd_autotune() measures instead), else 1, 2, 4, 8 or 16.  thermostat: 0 = NVE,
  * 1 = Berendsen with coupling time tau_fs (> 0), applied to the mobile atoms
  * at the end of each step. */
 typedef struct {
@@ -191,6 +192,16 @@ ptamd_status ptamd_set_stream(ptamd_system *sys, void *hip_stream);
 /* Average duration in ms of the force kernel over the launches it timed with
  * HIP events on the system's stream since the last reset, and the count. */
 ptamd_status ptamd_kernel_timing(ptamd_system *sys, double *avg_ms, int64_t *count, int32_t reset);
+/* Autotuner: times probe bursts of probe_steps (>= 10) steps from the
+ * current state for lanes per atom in {2, 4, 8, 16} and Verlet skin in
+ * {0.6, 1.0, 1.5} A, keeps the fastest, and restores the state exactly
+ * (positions, velocities, atom order).  With use_cache != 0 an earlier
+ * choice for the same atom count, replica count, precision and cutoff in
+ * this process is reused without probing.  The choice changes summation
+ * order (hence rounding), never the computed quantities.  Outputs may be
+ * NULL. */
+ptamd_status ptamd_autotune(ptamd_system *sys, int64_t probe_steps, int32_t use_cache, int32_t *lanes_per_atom,
+                            double *skin, double *ms_per_step);
 /* Unique pairs within rc at the current positions (for the algorithmic
  * flop count), per replica summed. */
 ptamd_status ptamd_count_pairs(ptamd_system *sys, int64_t *pairs_in_rc, int64_t *list_entries);

@@ -98,6 +98,7 @@ SIGNATURES = {
     "ptamd_get_info": [_SYS, C.POINTER(Info)],
     "ptamd_set_stream": [_SYS, C.c_void_p],
     "ptamd_kernel_timing": [_SYS, _D, C.POINTER(C.c_int64), C.c_int32],
+    "ptamd_autotune": [_SYS, C.c_int64, C.c_int32, C.POINTER(C.c_int32), _D, _D],
     "ptamd_count_pairs": [_SYS, C.POINTER(C.c_int64), C.POINTER(C.c_int64)],
     "ptamd_last_error": [],
     "ptamd_version": [],
@@ -272,6 +273,12 @@ def kernel_timing(sys: int, reset: bool = False):
     return ms.value, cnt.value
 
 
+def autotune(sys: int, probe_steps: int = 100, use_cache: bool = True) -> dict:
+    l, sk, ms = C.c_int32(), C.c_double(), C.c_double()
+    _check(_lib.ptamd_autotune(sys, probe_steps, int(use_cache), C.byref(l), C.byref(sk), C.byref(ms)))
+    return {"lanes_per_atom": l.value, "skin": sk.value, "ms_per_step": ms.value}
+
+
 def count_pairs(sys: int):
     p, e = C.c_int64(), C.c_int64()
     _check(_lib.ptamd_count_pairs(sys, C.byref(p), C.byref(e)))
@@ -364,3 +371,6 @@ class System:
 
     def count_pairs(self):
         return count_pairs(self.h)
+
+    def autotune(self, probe_steps: int = 100, use_cache: bool = True):
+        return autotune(self.h, probe_steps, use_cache)

@@ -1,12 +1,12 @@
 // gfx950 kernels of the EAM molecular-dynamics burst.
 //
-// One MD step is three launches, captured in a HIP graph per chunk of steps:
+// One MD step is three launches, captured in a HIP graph per chunk of steps
+// (a chunk may start with a Verlet-list build, scheduled by the host):
 //   kick_drift : Berendsen lambda of the previous step from the fixed-point
 //                slot sums, v <- lambda v + dt/(2m) F, x <- x + dt v
 //                (Eqs. (vv_algo_pos_pred_half), (vv_algo_pos_pred)); records
 //                the previous step's sample (Eq. (R_m_t)).
-//   density    : rebuilds the Verlet lists when flagged, then the host
-//                density rhobar_i and B'(rhobar_i) of Eq. (pe).
+//   density    : the host density rhobar_i and B'(rhobar_i) of Eq. (pe).
 //   force      : F^int of Eq. (f_int), pair energy, virial W_zz, reaction;
 //                second half kick (Eq. (vv_algo_vel_pred)); fixed-point
 //                block sums into the slots.
@@ -18,6 +18,8 @@
 #include "ptamd_internal.h"
 
 #include <math.h>
+
+#include <algorithm>
 
 namespace ptamd {
 
@@ -62,6 +64,29 @@ template <class R> __device__ __forceinline__ R ipow(R x, int e) {
   return r;
 }
 
+// (a/r)^n and (a/r)^m.  NM = 1 is the Sutton-Chen aluminium pair n = 7,
+// m = 6: t^6 = (t^2)^3, t^7 = t^6 t; NM = 0 takes any integer exponents.
+template <class R, int NM>
+__device__ __forceinline__ void sc_powers(R t, int n, int m, R *tn, R *tm) {
+  if (NM == 1) {
+    const R t2 = t * t;
+    const R t6 = t2 * t2 * t2;
+    *tm = t6;
+    *tn = t6 * t;
+  } else {
+    *tm = ipow<R>(t, m);
+    *tn = ipow<R>(t, n);
+  }
+}
+
+template <class R, int NM> __device__ __forceinline__ R rho_pow(R t, int m) {
+  if (NM == 1) {
+    const R t2 = t * t;
+    return t2 * t2 * t2;
+  }
+  return ipow<R>(t, m);
+}
+
 __device__ __forceinline__ float rsqrt_r(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double rsqrt_r(double x) { return rsqrt(x); }
 
@@ -86,6 +111,33 @@ __device__ __forceinline__ void block_slot_add(long long (&v)[NQ], unsigned long
   }
 }
 
+// Block sum of per-atom fixed-point values when one lane per atom holds
+// them (APB atoms per block): through LDS instead of wavefront shuffles.
+// Every atom's owner lane must call with owner = true (zeros for padding),
+// so that all APB rows are written.
+template <int NQ, int APB>
+__device__ __forceinline__ void block_atoms_add(const long long (&v)[NQ], bool owner, int atom, unsigned long long *row) {
+  __shared__ long long sh[APB][NQ];
+  __shared__ long long part[NQ][8];
+  if (owner)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) sh[atom][q] = v[q];
+  __syncthreads();
+  if (threadIdx.x < NQ * 8) {
+    const int q = threadIdx.x >> 3, p8 = threadIdx.x & 7;
+    long long t = 0;
+    for (int a = p8; a < APB; a += 8) t += sh[a][q];
+    part[q][p8] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x < NQ) {
+    long long t = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) t += part[threadIdx.x][k];
+    if (t != 0) atomicAdd(row + threadIdx.x, (unsigned long long)t);
+  }
+}
+
 __device__ __forceinline__ unsigned long long *slot_row(const Buffers &b, int n_rep, int par, int r, int slot) {
   return b.slots + (((size_t)par * n_rep + r) * kSlots + slot) * kNQ;
 }
@@ -106,6 +158,7 @@ __global__ void k_burst_begin(Buffers b, int n_rep) {
 }
 
 __global__ void k_set_base(Control *ctl, int64_t base) { ctl->base = base; }
+__global__ void k_set_ncells(Control *ctl, int64_t n) { ctl->ncells = n; }
 
 __global__ void k_fill_u64(unsigned long long *p, int64_t n, unsigned long long v) {
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
@@ -185,15 +238,35 @@ template <class R>
 __global__ __launch_bounds__(kBlock) void k_kick_drift(Params p, Buffers b, int32_t k, int32_t mode) {
   using V4 = typename V4T<R>::T;
   const int64_t tile = blockIdx.x;
-  const int r = b.blk_rep[tile];
+  const int r = (p.n_rep == 1) ? 0 : b.blk_rep[tile];
+  const int64_t i = tile * kTile + threadIdx.x;
+  // per-atom loads first: they stay in flight while wave 0 reduces lambda
+  // every array covers the padded range, so these loads need not wait for the group
+  const bool mob = b.group[i] == 0;
+  double vx = b.vx[i], vy = b.vy[i], vz = b.vz[i];
+  double x = 0, y = 0, z = 0, fx = 0, fy = 0, fz = 0;
+  float xr = 0.f, yr = 0.f, zr = 0.f;
+  if (mode == 0) {
+    fx = b.fx[i]; fy = b.fy[i]; fz = b.fz[i];
+    x = b.x[i]; y = b.y[i]; z = b.z[i];
+    xr = b.xr[i]; yr = b.yr[i]; zr = b.zr[i];
+  }
   const int64_t step = b.ctl->base + k;  // mode 0: step being computed; mode 1: n_steps + 1
   __shared__ double s_lam;
   if (threadIdx.x < 64) {
-    long long q[6] = {0, 0, 0, 0, 0, 0};
-    if (step > 1) {
-      const unsigned long long *row = slot_row(b, p.n_rep, (int)((step - 1) & 1), r, threadIdx.x);
+    // both parities' rows are loaded before the step index arrives
+    const unsigned long long *row0 = slot_row(b, p.n_rep, 0, r, threadIdx.x);
+    const unsigned long long *row1 = slot_row(b, p.n_rep, 1, r, threadIdx.x);
+    long long q0[6], q1[6], q[6];
 #pragma unroll
-      for (int t = 0; t < 6; ++t) q[t] = (long long)row[t];
+    for (int t = 0; t < 6; ++t) {
+      q0[t] = (long long)row0[t];
+      q1[t] = (long long)row1[t];
+    }
+    const bool odd = ((step - 1) & 1) != 0;
+#pragma unroll
+    for (int t = 0; t < 6; ++t) q[t] = (step > 1) ? (odd ? q1[t] : q0[t]) : 0;
+    if (step > 1) {
 #pragma unroll
       for (int t = 0; t < 6; ++t)
 #pragma unroll
@@ -223,17 +296,18 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(Params p, Buffers b, int3
     }
   }
   __syncthreads();
+  if (!mob) return;  // fixed or padding atom: v = 0, never moves
   const double lam = s_lam;
-  const int64_t i = tile * kTile + threadIdx.x;
-  if (b.group[i] != 0) return;  // fixed or padding atom: v = 0, never moves
-  double vx = b.vx[i] * lam, vy = b.vy[i] * lam, vz = b.vz[i] * lam;
+  vx *= lam;
+  vy *= lam;
+  vz *= lam;
   if (mode == 0) {
-    vx += p.hdt_m * b.fx[i];
-    vy += p.hdt_m * b.fy[i];
-    vz += p.hdt_m * b.fz[i];
-    const double x = b.x[i] + p.dt * vx;
-    const double y = b.y[i] + p.dt * vy;
-    const double z = b.z[i] + p.dt * vz;
+    vx += p.hdt_m * fx;
+    vy += p.hdt_m * fy;
+    vz += p.hdt_m * fz;
+    x += p.dt * vx;
+    y += p.dt * vy;
+    z += p.dt * vz;
     b.x[i] = x;
     b.y[i] = y;
     b.z[i] = z;
@@ -247,8 +321,8 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(Params p, Buffers b, int3
     const RepInfo &rp = b.rep[r];
     const double cx = x - rp.center[0], cy = y - rp.center[1], cz = z - rp.center[2];
     if (!(cx * cx + cy * cy + cz * cz <= p.esc2)) set_err(b, isfinite(x + y + z) ? E_ESCAPE : E_NONFINITE);
-    const double ex = x - (double)b.xr[i], ey = y - (double)b.yr[i], ez = z - (double)b.zr[i];
-    if (ex * ex + ey * ey + ez * ez > p.half_skin2) b.ctl->rebuild = 1;
+    const double ex = x - (double)xr, ey = y - (double)yr, ez = z - (double)zr;
+    if (ex * ex + ey * ey + ez * ez > p.half_skin2) set_err(b, E_SKIN);
   }
   b.vx[i] = vx;
   b.vy[i] = vy;
@@ -270,58 +344,114 @@ __global__ __launch_bounds__(kBlock) void k_pos4(Buffers b) {
 }
 
 // ---------------------------------------------------------------------------
-// density pass (+ Verlet-list rebuild when flagged)
+// density pass
 // ---------------------------------------------------------------------------
-template <int LPA>
-__device__ void build_list(const Params &p, const Buffers &b, int64_t i, int lane, int r) {
+// ---------------------------------------------------------------------------
+// Verlet-list build
+// ---------------------------------------------------------------------------
+// Atom i's list holds every j != i within rlist.  Candidates come from the
+// 5 x 5 x 5 bins around the bin i was sorted into: the bin edge is
+// (rlist + 2 margin)/2, so the stencil reaches every atom within rlist while
+// no atom has drifted more than the margin from its sorted position (checked
+// here: E_DRIFT).  Bins of one stencil row (fixed y, z; consecutive x) are
+// consecutive in the sorted order, so a row is one contiguous range of
+// atoms.  Rows and bins whose box (open outward at the grid edge, where far
+// atoms are clamped) lies farther than rlist + margin from atom i are
+// skipped.  KB lanes share one atom; list positions come from a ballot
+// prefix, so the order is fixed: rows in stencil order, atoms in sorted order.
+constexpr int KB = 16;   // lanes per atom in the list build
+constexpr int KCH = 4;   // candidates per lane per pass, loaded before use
+
+__device__ __forceinline__ double box_dist(double v, double o, double h, int n, int dim) {
+  const double lo = (n == 0) ? -1e300 : o + n * h;
+  const double hi = (n == dim - 1) ? 1e300 : o + (n + 1) * h;
+  return fmax(fmax(lo - v, v - hi), 0.0);
+}
+
+// Decided in FP64 with the plain formula (no contraction): the same rounding
+// as the oracle.  An FP32 copy settles candidates away from the boundary.
+__device__ __forceinline__ bool in_list(const Params &p, const Buffers &b, int j, float4 q, float4 pi, double xi,
+                                        double yi, double zi) {
+  const float dx = q.x - pi.x, dy = q.y - pi.y, dz = q.z - pi.z;
+  const float d2 = dx * dx + dy * dy + dz * dz;
+  if (d2 < p.rlist2_lo) return true;
+  if (d2 > p.rlist2_hi) return false;
+  return dist2_plain(sub_plain(b.x[j], xi), sub_plain(b.y[j], yi), sub_plain(b.z[j], zi)) < p.rlist2;
+}
+
+template <class R> __device__ __forceinline__ float4 to_f4(typename V4T<R>::T v) {
+  return make_float4((float)v.x, (float)v.y, (float)v.z, 0.f);
+}
+
+template <class R, int LPA>
+__device__ void build_one(const Params &p, const Buffers &b, int64_t i, int lane) {
+  using V4 = typename V4T<R>::T;
+  const int r = b.blk_rep[i / kTile];
+  const V4 *p4 = reinterpret_cast<const V4 *>(b.pos4);
   const RepInfo &rp = b.rep[r];
   const double xi = b.x[i], yi = b.y[i], zi = b.z[i];
-  {
+  const float4 pi = make_float4((float)xi, (float)yi, (float)zi, 0.f);
+  if (lane == 0) {
     const double ex = xi - (double)b.xs[i], ey = yi - (double)b.ys[i], ez = zi - (double)b.zs[i];
-    if (lane == 0 && ex * ex + ey * ey + ez * ez > p.margin2) set_err(b, E_DRIFT);
+    if (ex * ex + ey * ey + ez * ez > p.margin2) set_err(b, E_DRIFT);
   }
   const int dxn = rp.dims[0], dyn = rp.dims[1], dzn = rp.dims[2];
+  const double hb = p.bin_h;
   const int cl = b.cell[i];
   const int cx = cl % dxn, cy = (cl / dxn) % dyn, cz = cl / (dxn * dyn);
-  const int gbase = (threadIdx.x & 63) & ~(LPA - 1);
-  const unsigned long long gmask = (LPA == 64) ? ~0ull : ((1ull << LPA) - 1ull);
+  // phase 1: lane l resolves stencil rows l and l + 16 into atom ranges
+  int rs[2] = {0, 0}, re[2] = {0, 0};
+#pragma unroll
+  for (int h2 = 0; h2 < 2; ++h2) {
+    const int q = lane + h2 * KB;
+    if (q >= 25) continue;
+    const int nz = cz + q / 5 - 2, ny = cy + q % 5 - 2;
+    if (nz < 0 || nz >= dzn || ny < 0 || ny >= dyn) continue;
+    const double dz = box_dist(zi, rp.origin[2], hb, nz, dzn), dy = box_dist(yi, rp.origin[1], hb, ny, dyn);
+    const double dyz = dy * dy + dz * dz;
+    if (dyz > p.cull2) continue;
+    int lo = max(cx - 2, 0), hi = min(cx + 2, dxn - 1);
+    while (lo <= hi) {
+      const double d = box_dist(xi, rp.origin[0], hb, lo, dxn);
+      if (d * d + dyz <= p.cull2) break;
+      ++lo;
+    }
+    while (hi >= lo) {
+      const double d = box_dist(xi, rp.origin[0], hb, hi, dxn);
+      if (d * d + dyz <= p.cull2) break;
+      --hi;
+    }
+    if (lo > hi) continue;
+    const int64_t row = rp.cell_off + ((int64_t)nz * dyn + ny) * dxn;
+    rs[h2] = b.cell_start[row + lo];
+    re[h2] = b.cell_start[row + hi] + b.cell_count[row + hi];
+  }
+  // phase 2: scan the rows in order, KB x KCH candidates per pass
+  const int gbase = (threadIdx.x & 63) & ~(KB - 1);
+  const unsigned long long gmask = (1ull << KB) - 1ull;
   const unsigned long long below = (1ull << lane) - 1ull;
-  int cnt = 0;
   const int cap = p.cap_slots * LPA;
-  for (int oz = -1; oz <= 1; ++oz) {
-    const int nz = cz + oz;
-    if (nz < 0 || nz >= dzn) continue;
-    for (int oy = -1; oy <= 1; ++oy) {
-      const int ny = cy + oy;
-      if (ny < 0 || ny >= dyn) continue;
-      for (int ox = -1; ox <= 1; ++ox) {
-        const int nx = cx + ox;
-        if (nx < 0 || nx >= dxn) continue;
-        const int64_t c = rp.cell_off + ((int64_t)nz * dyn + ny) * dxn + nx;
-        const int start = b.cell_start[c], count = b.cell_count[c];
-        for (int t = 0; t < count; t += LPA) {
-          const int jj = t + lane;
-          bool ok = false;
-          int j = 0;
-          if (jj < count) {
-            j = start + jj;
-            if ((int64_t)j != i) {
-              const double d2 = dist2_plain(sub_plain(b.x[j], xi), sub_plain(b.y[j], yi), sub_plain(b.z[j], zi));
-              ok = d2 < p.rlist2;
-            }
-          }
-          int pos, add;
-          if (LPA == 1) {
-            pos = cnt;
-            add = ok ? 1 : 0;
-          } else {
-            const unsigned long long m = (__ballot(ok) >> gbase) & gmask;
-            pos = cnt + __popcll(m & below);
-            add = __popcll(m);
-          }
-          if (ok && pos < cap) b.nbr[(size_t)(pos / LPA) * p.nbr_stride + (size_t)i * LPA + (pos % LPA)] = j;
-          cnt += add;
-        }
+  int cnt = 0;
+  for (int q = 0; q < 25; ++q) {
+    const int src = gbase + (q % KB);
+    const int s0 = __shfl(q < KB ? rs[0] : rs[1], src);
+    const int e0 = __shfl(q < KB ? re[0] : re[1], src);
+    for (int t = s0; t < e0; t += KB * KCH) {
+      int jc[KCH];
+      float4 qv[KCH];
+#pragma unroll
+      for (int u = 0; u < KCH; ++u) {
+        jc[u] = t + u * KB + lane;
+        qv[u] = to_f4<R>(p4[min(jc[u], e0 - 1)]);
+      }
+#pragma unroll
+      for (int u = 0; u < KCH; ++u) {
+        const int j = jc[u];
+        const bool ok = j < e0 && (int64_t)j != i && in_list(p, b, j, qv[u], pi, xi, yi, zi);
+        const unsigned long long m = (__ballot(ok) >> gbase) & gmask;
+        const int pos = cnt + __popcll(m & below);
+        if (ok && pos < cap) b.nbr[nbr_index(i, pos, LPA, p.nbr_stride)] = j;
+        cnt += __popcll(m);
       }
     }
   }
@@ -337,7 +467,16 @@ __device__ void build_list(const Params &p, const Buffers &b, int64_t i, int lan
   }
 }
 
+// Grid-stride over atoms: KB lanes per atom.
 template <class R, int LPA>
+__global__ __launch_bounds__(kBlock) void k_build(Params p, Buffers b) {
+  const int lane = (int)(threadIdx.x & (KB - 1));
+  const int64_t per_pass = (int64_t)gridDim.x * (kBlock / KB);
+  for (int64_t i = (int64_t)blockIdx.x * (kBlock / KB) + threadIdx.x / KB; i < p.ntot; i += per_pass)
+    if (b.group[i] != kPad) build_one<R, LPA>(p, b, i, lane);  // a lane group skips together
+}
+
+template <class R, int LPA, int NM>
 __global__ __launch_bounds__(kBlock) void k_density(Params p, Buffers b, int32_t k) {
   using V4 = typename V4T<R>::T;
   const int64_t gt = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -347,7 +486,6 @@ __global__ __launch_bounds__(kBlock) void k_density(Params p, Buffers b, int32_t
   const int r = b.blk_rep[tile];
   const int64_t step = b.ctl->base + k;
   const int par = (int)(step & 1);
-  const bool rebuild = b.ctl->rebuild != 0;
   {
     // the slots of the other parity were consumed by this step's kick-drift
     const size_t nz = (size_t)p.n_rep * kSlots * kNQ;
@@ -356,24 +494,34 @@ __global__ __launch_bounds__(kBlock) void k_density(Params p, Buffers b, int32_t
   }
   const uint8_t g = b.group[i];
   const bool real = g != kPad;
-  if (rebuild && real) build_list<LPA>(p, b, i, lane, r);
   const V4 *p4 = reinterpret_cast<const V4 *>(b.pos4);
   R acc = (R)0;
   if (real) {
     const V4 pi = p4[i];
     const R rc2 = (R)p.rc2, a = (R)p.a, rc = (R)p.rc, rhoc = (R)p.rhoc, drhoc = (R)p.drhoc;
     const int cnt = b.ncount[i];
-    const int32_t *nb = b.nbr + (size_t)i * LPA + lane;
-    for (int e = lane, s = 0; e < cnt; e += LPA, ++s) {
-      const int j = nb[(size_t)s * p.nbr_stride];
-      const V4 pj = p4[j];
-      const R dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
-      const R r2 = dx * dx + dy * dy + dz * dz;
-      if (r2 < rc2) {
-        const R rinv = rsqrt_r(r2);
-        const R rr = r2 * rinv;
-        const R rho = ipow<R>(a * rinv, p.m);
-        acc += rho - rhoc - (rr - rc) * drhoc;
+    const int my = (cnt > lane) ? (cnt - lane + LPA - 1) / LPA : 0;
+    const int4 *nb4 = reinterpret_cast<const int4 *>(b.nbr) + (size_t)i * LPA + lane;
+    // two groups of four indices per pass: eight independent gathers in flight
+    for (int s = 0; s < my; s += 2 * kGroup) {
+      const int4 ja = nb4[(size_t)(s / kGroup) * p.nbr_stride];
+      const int4 jb = (s + kGroup < my) ? nb4[(size_t)(s / kGroup + 1) * p.nbr_stride] : make_int4(0, 0, 0, 0);
+      const int rem = my - s;
+      const int ii = (int)i;
+      const int jv[8] = {ja.x, rem > 1 ? ja.y : ii, rem > 2 ? ja.z : ii, rem > 3 ? ja.w : ii,
+                         rem > 4 ? jb.x : ii, rem > 5 ? jb.y : ii, rem > 6 ? jb.z : ii, rem > 7 ? jb.w : ii};
+      V4 pj[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) pj[u] = p4[jv[u]];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const R dx = pj[u].x - pi.x, dy = pj[u].y - pi.y, dz = pj[u].z - pi.z;
+        const R r2 = dx * dx + dy * dy + dz * dz;
+        if (u < rem && r2 < rc2) {
+          const R rinv = rsqrt_r(r2);
+          const R rr = r2 * rinv;
+          acc += rho_pow<R, NM>(a * rinv, p.m) - rhoc - (rr - rc) * drhoc;
+        }
       }
     }
   }
@@ -391,13 +539,14 @@ __global__ __launch_bounds__(kBlock) void k_density(Params p, Buffers b, int32_t
     reinterpret_cast<R *>(b.pos4)[4 * i + 3] = (R)Bp;
     q[0] = to_fix(B);
   }
-  block_slot_add<1>(q, slot_row(b, p.n_rep, par, r, blockIdx.x & (kSlots - 1)) + Q_EMB);
+  block_atoms_add<1, kBlock / LPA>(q, lane == 0, threadIdx.x / LPA,
+                                   slot_row(b, p.n_rep, par, r, blockIdx.x & (kSlots - 1)) + Q_EMB);
 }
 
 // ---------------------------------------------------------------------------
 // force pass: mode 0 = step (second half kick + sums), 1 = forces only
 // ---------------------------------------------------------------------------
-template <class R, int LPA>
+template <class R, int LPA, int NM>
 __global__ __launch_bounds__(kBlock) void k_force(Params p, Buffers b, int32_t k, int32_t mode) {
   using V4 = typename V4T<R>::T;
   const int64_t gt = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -418,29 +567,40 @@ __global__ __launch_bounds__(kBlock) void k_force(Params p, Buffers b, int32_t k
     const R nn = (R)p.n, mm = (R)p.m;
     const R Vc = (R)p.Vc, dVc = (R)p.dVc, drhoc = (R)p.drhoc;
     const int cnt = b.ncount[i];
-    const int32_t *nb = b.nbr + (size_t)i * LPA + lane;
-    for (int e = lane, s = 0; e < cnt; e += LPA, ++s) {
-      const int j = nb[(size_t)s * p.nbr_stride];
-      const V4 pj = p4[j];
-      const R dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
-      const R r2 = dx * dx + dy * dy + dz * dz;
-      if (r2 < rc2) {
-        const R rinv = rsqrt_r(r2);
-        const R rr = r2 * rinv;
-        const R t = a * rinv;
-        const R V = eps * ipow<R>(t, p.n);
-        const R rho = ipow<R>(t, p.m);
-        const R dV = -nn * V * rinv;
-        const R drho = -mm * rho * rinv;
-        const R Vs = V - Vc - (rr - rc) * dVc;
-        const R gg = (dV - dVc) + (pi.w + pj.w) * (drho - drhoc);
-        const R f = gg * rinv;
-        fx += f * dx;
-        fy += f * dy;
-        fz += f * dz;
-        ep += Vs;
-        w += f * dz * dz;
-        ++npair;
+    const int my = (cnt > lane) ? (cnt - lane + LPA - 1) / LPA : 0;
+    const int4 *nb4 = reinterpret_cast<const int4 *>(b.nbr) + (size_t)i * LPA + lane;
+    for (int s = 0; s < my; s += 2 * kGroup) {
+      const int4 ja = nb4[(size_t)(s / kGroup) * p.nbr_stride];
+      const int4 jb = (s + kGroup < my) ? nb4[(size_t)(s / kGroup + 1) * p.nbr_stride] : make_int4(0, 0, 0, 0);
+      const int rem = my - s;
+      const int ii = (int)i;
+      const int jv[8] = {ja.x, rem > 1 ? ja.y : ii, rem > 2 ? ja.z : ii, rem > 3 ? ja.w : ii,
+                         rem > 4 ? jb.x : ii, rem > 5 ? jb.y : ii, rem > 6 ? jb.z : ii, rem > 7 ? jb.w : ii};
+      V4 pj[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) pj[u] = p4[jv[u]];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const R dx = pj[u].x - pi.x, dy = pj[u].y - pi.y, dz = pj[u].z - pi.z;
+        const R r2 = dx * dx + dy * dy + dz * dz;
+        if (u < rem && r2 < rc2) {
+          const R rinv = rsqrt_r(r2);
+          const R rr = r2 * rinv;
+          R tn, tm;
+          sc_powers<R, NM>(a * rinv, p.n, p.m, &tn, &tm);
+          const R V = eps * tn;
+          const R dV = -nn * V * rinv;
+          const R drho = -mm * tm * rinv;
+          const R Vs = V - Vc - (rr - rc) * dVc;
+          const R gg = (dV - dVc) + (pi.w + pj[u].w) * (drho - drhoc);
+          const R f = gg * rinv;
+          fx += f * dx;
+          fy += f * dy;
+          fz += f * dz;
+          ep += Vs;
+          w += f * dz * dz;
+          ++npair;
+        }
       }
     }
   }
@@ -478,11 +638,9 @@ __global__ __launch_bounds__(kBlock) void k_force(Params p, Buffers b, int32_t k
     if (g == 2) q[Q_RZ] = to_fix(-Fz);
     q[Q_PAIRS] = npair;
   }
-  block_slot_add<kNQ>(q, slot_row(b, p.n_rep, par, r, blockIdx.x & (kSlots - 1)));
-  if (gt == 0 && b.ctl->rebuild) {
-    b.ctl->list_builds += 1;
-    b.ctl->rebuild = 0;
-  }
+  block_atoms_add<kNQ, kBlock / LPA>(q, lane == 0, threadIdx.x / LPA,
+                                     slot_row(b, p.n_rep, par, r, blockIdx.x & (kSlots - 1)));
+
 }
 
 // ---------------------------------------------------------------------------
@@ -490,79 +648,76 @@ __global__ __launch_bounds__(kBlock) void k_force(Params p, Buffers b, int32_t k
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ unsigned long long dbits(double v) { return (unsigned long long)__double_as_longlong(v); }
 
-__global__ __launch_bounds__(kBlock) void k_chunk_stats(Params p, Buffers b) {
-  const int64_t tile = blockIdx.x;
-  const int r = b.blk_rep[tile];
-  const int64_t i = tile * kTile + threadIdx.x;
-  double d2 = 0.0, v2 = 0.0;
-  if (b.group[i] == 0) {
-    const double ex = b.x[i] - (double)b.xs[i], ey = b.y[i] - (double)b.ys[i], ez = b.z[i] - (double)b.zs[i];
-    d2 = ex * ex + ey * ey + ez * ez;
-    v2 = b.vx[i] * b.vx[i] + b.vy[i] * b.vy[i] + b.vz[i] * b.vz[i];
-    if (!isfinite(d2 + v2)) {
-      set_err(b, E_NONFINITE);
-      d2 = v2 = 0.0;
-    }
-  }
-  for (int o = 32; o > 0; o >>= 1) {
-    d2 = fmax(d2, __shfl_xor(d2, o));
-    v2 = fmax(v2, __shfl_xor(v2, o));
-  }
-  __shared__ double sh[kBlock / 64][2];
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  if (lane == 0) {
-    sh[wid][0] = d2;
-    sh[wid][1] = v2;
-  }
-  __syncthreads();
-  if (threadIdx.x < 2) {
-    double m = 0.0;
-    for (int w2 = 0; w2 < kBlock / 64; ++w2) m = fmax(m, sh[w2][threadIdx.x]);
-    atomicMax(b.stat + ((size_t)r * kSlots + (blockIdx.x & (kSlots - 1))) * 4 + threadIdx.x, dbits(m));
-  }
-}
-
-// ---------------------------------------------------------------------------
-// spatial sort
-// ---------------------------------------------------------------------------
 // order-preserving map of a double onto uint64 (for min/max atomics)
 __device__ __forceinline__ unsigned long long okey(double v) {
   unsigned long long u = dbits(v);
   return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
 }
 
-__global__ __launch_bounds__(kBlock) void k_bbox(Params p, Buffers b) {
+// stat rows: [replica][slot][kStat] = drift^2, v^2 (max, double bits), min
+// x,y,z and max x,y,z (order-preserving keys), displacement^2 since the list
+// build (max, double bits)
+__global__ void k_stat_init(unsigned long long *stat, int64_t rows) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < rows * kStat;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(t % kStat);
+    stat[t] = (c >= 2 && c < 5) ? ~0ull : 0ull;
+  }
+}
+
+// Chunk-end statistics per replica: max drift since the last sort, max
+// speed and max displacement since the list build of the mobile atoms, and
+// the bounding box of all real atoms (the grid of the next sort).
+__global__ __launch_bounds__(kBlock) void k_chunk_stats(Params p, Buffers b) {
   const int64_t tile = blockIdx.x;
   const int r = b.blk_rep[tile];
   const int64_t i = tile * kTile + threadIdx.x;
+  double d2 = 0.0, v2 = 0.0, l2 = 0.0;
   unsigned long long mn[3] = {~0ull, ~0ull, ~0ull}, mx[3] = {0ull, 0ull, 0ull};
-  if (b.group[i] != kPad) {
-    const double c[3] = {b.x[i], b.y[i], b.z[i]};
-    for (int d = 0; d < 3; ++d) {
-      mn[d] = okey(c[d]);
-      mx[d] = mn[d];
+  const uint8_t g = b.group[i];
+  if (g != kPad) {
+    const double x = b.x[i], y = b.y[i], z = b.z[i];
+    const double c[3] = {x, y, z};
+    for (int d = 0; d < 3; ++d) mn[d] = mx[d] = okey(c[d]);
+    if (g == 0) {
+      const double ex = x - (double)b.xs[i], ey = y - (double)b.ys[i], ez = z - (double)b.zs[i];
+      d2 = ex * ex + ey * ey + ez * ez;
+      const double fx = x - (double)b.xr[i], fy = y - (double)b.yr[i], fz = z - (double)b.zr[i];
+      l2 = fx * fx + fy * fy + fz * fz;
+      v2 = b.vx[i] * b.vx[i] + b.vy[i] * b.vy[i] + b.vz[i] * b.vz[i];
+    }
+    if (!isfinite(x + y + z + d2 + v2 + l2)) {
+      set_err(b, E_NONFINITE);
+      d2 = v2 = l2 = 0.0;
     }
   }
-  __shared__ unsigned long long sh[kBlock / 64][6];
-  for (int d = 0; d < 3; ++d)
-    for (int o = 32; o > 0; o >>= 1) {
-      const long long a = shfl_xor_ll((long long)mn[d], o), c2 = shfl_xor_ll((long long)mx[d], o);
-      mn[d] = min(mn[d], (unsigned long long)a);
-      mx[d] = max(mx[d], (unsigned long long)c2);
-    }
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  if (lane == 0)
+  for (int o = 32; o > 0; o >>= 1) {
+    d2 = fmax(d2, __shfl_xor(d2, o));
+    v2 = fmax(v2, __shfl_xor(v2, o));
+    l2 = fmax(l2, __shfl_xor(l2, o));
     for (int d = 0; d < 3; ++d) {
-      sh[wid][d] = mn[d];
-      sh[wid][3 + d] = mx[d];
+      mn[d] = min(mn[d], (unsigned long long)shfl_xor_ll((long long)mn[d], o));
+      mx[d] = max(mx[d], (unsigned long long)shfl_xor_ll((long long)mx[d], o));
     }
+  }
+  __shared__ unsigned long long sh[kBlock / 64][9];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) {
+    sh[wid][0] = dbits(d2);
+    sh[wid][1] = dbits(v2);
+    for (int d = 0; d < 3; ++d) {
+      sh[wid][2 + d] = mn[d];
+      sh[wid][5 + d] = mx[d];
+    }
+    sh[wid][8] = dbits(l2);
+  }
   __syncthreads();
-  if (threadIdx.x < 6) {
-    const int d = threadIdx.x;
-    unsigned long long v = sh[0][d];
-    for (int w2 = 1; w2 < kBlock / 64; ++w2) v = (d < 3) ? min(v, sh[w2][d]) : max(v, sh[w2][d]);
-    unsigned long long *dst = b.stat + ((size_t)r * kSlots + (blockIdx.x & (kSlots - 1))) * 8 + d;
-    if (d < 3) atomicMin(dst, v);
+  if (threadIdx.x < 9) {
+    const int c = threadIdx.x;
+    unsigned long long v = sh[0][c];
+    for (int w2 = 1; w2 < kBlock / 64; ++w2) v = (c >= 2 && c < 5) ? min(v, sh[w2][c]) : max(v, sh[w2][c]);
+    unsigned long long *dst = b.stat + ((size_t)r * kSlots + (blockIdx.x & (kSlots - 1))) * kStat + c;
+    if (c >= 2 && c < 5) atomicMin(dst, v);
     else atomicMax(dst, v);
   }
 }
@@ -574,22 +729,32 @@ __device__ __forceinline__ int cell_coord(double v, double o, double inv_h, int 
   return (int)t;
 }
 
+__device__ __forceinline__ int atom_cell(const Buffers &b, const RepInfo &rp, int64_t i) {
+  if (b.group[i] == kPad) return (int)(rp.ncells - 1);  // virtual last cell: padding sorts to the end
+  const int cx = cell_coord(b.x[i], rp.origin[0], rp.inv_h, rp.dims[0]);
+  const int cy = cell_coord(b.y[i], rp.origin[1], rp.inv_h, rp.dims[1]);
+  const int cz = cell_coord(b.z[i], rp.origin[2], rp.inv_h, rp.dims[2]);
+  return (cz * rp.dims[1] + cy) * rp.dims[0] + cx;
+}
+
+// One atomic per distinct cell in a wave (atoms arrive nearly sorted, so a
+// wave touches few cells).
 __global__ __launch_bounds__(kBlock) void k_assign_count(Params p, Buffers b, int32_t *key) {
   const int64_t tile = blockIdx.x;
   const int r = b.blk_rep[tile];
   const int64_t i = tile * kTile + threadIdx.x;
   const RepInfo &rp = b.rep[r];
-  int c;
-  if (b.group[i] == kPad) {
-    c = (int)(rp.ncells - 1);  // virtual last cell: padding sorts to the end
-  } else {
-    const int cx = cell_coord(b.x[i], rp.origin[0], rp.inv_h, rp.dims[0]);
-    const int cy = cell_coord(b.y[i], rp.origin[1], rp.inv_h, rp.dims[1]);
-    const int cz = cell_coord(b.z[i], rp.origin[2], rp.inv_h, rp.dims[2]);
-    c = (cz * rp.dims[1] + cy) * rp.dims[0] + cx;
-  }
+  const int c = atom_cell(b, rp, i);
   key[i] = c;
-  atomicAdd(b.cell_count + rp.cell_off + c, 1);
+  const int lane = threadIdx.x & 63;
+  unsigned long long todo = __ballot(true);
+  while (todo) {
+    const int leader = __ffsll((long long)todo) - 1;
+    const int lk = __shfl(c, leader);
+    const unsigned long long m = __ballot(c == lk) & todo;
+    if (lane == leader) atomicAdd(b.cell_count + rp.cell_off + lk, __popcll(m));
+    todo &= ~m;
+  }
 }
 
 // exclusive scan of one replica's cell counts (one block per replica)
@@ -628,7 +793,22 @@ __global__ __launch_bounds__(kBlock) void k_scatter(Buffers b, const int32_t *ke
   const int64_t tile = blockIdx.x;
   const int r = b.blk_rep[tile];
   const int64_t i = tile * kTile + threadIdx.x;
-  const int pos = atomicAdd(cursor + b.rep[r].cell_off + key[i], 1);
+  const int64_t off = b.rep[r].cell_off;
+  const int c = key[i];
+  const int lane = threadIdx.x & 63;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  unsigned long long todo = __ballot(true);
+  int pos = 0;
+  while (todo) {
+    const int leader = __ffsll((long long)todo) - 1;
+    const int lk = __shfl(c, leader);
+    const unsigned long long m = __ballot(c == lk) & todo;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(cursor + off + lk, __popcll(m));
+    base = __shfl(base, leader);
+    if (c == lk) pos = base + __popcll(m & below);
+    todo &= ~m;
+  }
   tmp[pos] = (int32_t)i;
 }
 
@@ -640,17 +820,32 @@ __device__ __forceinline__ long long sort_key(const Buffers &b, int v) {
   return (o >= 0) ? (long long)o : ((1ll << 32) + (long long)v);
 }
 
+constexpr int kSortLds = 512;  // cells up to this size are ranked from LDS
+
 __global__ __launch_bounds__(kBlock) void k_cell_sort(Buffers b, const int32_t *tmp, int32_t *perm, int64_t ncells_tot) {
-  const int64_t c = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-  if (c >= ncells_tot) return;
-  const int lane = threadIdx.x & 63;
+  __shared__ long long keys[kBlock / 64][kSortLds];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t c = (int64_t)blockIdx.x * (kBlock / 64) + w;
+  if (c >= ncells_tot) return;  // no block-wide barrier below: waves are independent
   const int start = b.cell_start[c], cnt = b.cell_count[c];
-  for (int a = lane; a < cnt; a += 64) {
-    const int v = tmp[start + a];
-    const long long kv = sort_key(b, v);
-    int rank = 0;
-    for (int q = 0; q < cnt; ++q) rank += (sort_key(b, tmp[start + q]) < kv) ? 1 : 0;
-    perm[start + rank] = v;
+  if (cnt <= kSortLds) {
+    for (int a = lane; a < cnt; a += 64) keys[w][a] = sort_key(b, tmp[start + a]);
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    for (int a = lane; a < cnt; a += 64) {
+      const long long kv = keys[w][a];
+      int rank = 0;
+      for (int q = 0; q < cnt; ++q) rank += (keys[w][q] < kv) ? 1 : 0;
+      perm[start + rank] = tmp[start + a];
+    }
+  } else {
+    for (int a = lane; a < cnt; a += 64) {
+      const int v = tmp[start + a];
+      const long long kv = sort_key(b, v);
+      int rank = 0;
+      for (int q = 0; q < cnt; ++q) rank += (sort_key(b, tmp[start + q]) < kv) ? 1 : 0;
+      perm[start + rank] = v;
+    }
   }
 }
 
@@ -683,6 +878,21 @@ __global__ __launch_bounds__(kBlock) void k_permute(Buffers b, Buffers sc, const
   reinterpret_cast<V4 *>(sc.pos4)[i] = v;
 }
 
+// copy the permuted arrays back into the primary buffers (one launch)
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_copy_back(Buffers b, Buffers sc) {
+  using V4 = typename V4T<R>::T;
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  b.x[i] = sc.x[i]; b.y[i] = sc.y[i]; b.z[i] = sc.z[i];
+  b.vx[i] = sc.vx[i]; b.vy[i] = sc.vy[i]; b.vz[i] = sc.vz[i];
+  b.fx[i] = sc.fx[i]; b.fy[i] = sc.fy[i]; b.fz[i] = sc.fz[i];
+  b.group[i] = sc.group[i];
+  b.orig[i] = sc.orig[i];
+  b.cell[i] = sc.cell[i];
+  b.xs[i] = sc.xs[i]; b.ys[i] = sc.ys[i]; b.zs[i] = sc.zs[i];
+  reinterpret_cast<V4 *>(b.pos4)[i] = reinterpret_cast<const V4 *>(sc.pos4)[i];
+}
+
 __global__ __launch_bounds__(kBlock) void k_strain(Params p, Buffers b, const double *factor) {
   const int64_t tile = blockIdx.x;
   const int r = b.blk_rep[tile];
@@ -702,7 +912,7 @@ __global__ __launch_bounds__(kBlock) void k_count_pairs(Params p, Buffers b) {
     const int cnt = b.ncount[i];
     ne = cnt;
     for (int e = 0; e < cnt; ++e) {
-      const int j = b.nbr[(size_t)(e / p.lpa) * p.nbr_stride + (size_t)i * p.lpa + (e % p.lpa)];
+      const int j = b.nbr[nbr_index(i, e, p.lpa, p.nbr_stride)];
       const double d2 = dist2_plain(b.x[j] - b.x[i], b.y[j] - b.y[i], b.z[j] - b.z[i]);
       if (d2 < p.rc2) ++np;
     }
@@ -712,7 +922,7 @@ __global__ __launch_bounds__(kBlock) void k_count_pairs(Params p, Buffers b) {
     ne += (unsigned long long)shfl_xor_ll((long long)ne, o);
   }
   if ((threadIdx.x & 63) == 0) {
-    unsigned long long *row = b.stat + ((size_t)r * kSlots + (blockIdx.x & (kSlots - 1))) * 4;
+    unsigned long long *row = b.stat + ((size_t)r * kSlots + (blockIdx.x & (kSlots - 1))) * kStat;
     atomicAdd(row, np);
     atomicAdd(row + 1, ne);
   }
@@ -731,6 +941,10 @@ void launch_set_base(const Buffers &b, int64_t base, hipStream_t s) {
   hipLaunchKernelGGL(k_set_base, dim3(1), dim3(1), 0, s, b.ctl, base);
 }
 
+void launch_set_ncells(const Buffers &b, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_ncells, dim3(1), dim3(1), 0, s, b.ctl, n);
+}
+
 void launch_fill_i64(unsigned long long *ptr, int64_t n, unsigned long long v, hipStream_t s) {
   if (n <= 0) return;
   unsigned g = (unsigned)std::min<int64_t>((n + kBlock - 1) / kBlock, 1024);
@@ -747,47 +961,72 @@ void launch_pos4(const Params &p, const Buffers &b, int precision, hipStream_t s
   else hipLaunchKernelGGL(k_pos4<double>, dim3(tiles(p)), dim3(kBlock), 0, s, b);
 }
 
-template <class R>
+template <class R, int NM>
 static void density_lpa(const Params &p, const Buffers &b, int lpa, int32_t k, hipStream_t s) {
   const unsigned g = (unsigned)(p.ntot * lpa / kBlock);
   switch (lpa) {
-    case 1: hipLaunchKernelGGL((k_density<R, 1>), dim3(g), dim3(kBlock), 0, s, p, b, k); break;
-    case 2: hipLaunchKernelGGL((k_density<R, 2>), dim3(g), dim3(kBlock), 0, s, p, b, k); break;
-    case 4: hipLaunchKernelGGL((k_density<R, 4>), dim3(g), dim3(kBlock), 0, s, p, b, k); break;
-    case 8: hipLaunchKernelGGL((k_density<R, 8>), dim3(g), dim3(kBlock), 0, s, p, b, k); break;
-    default: hipLaunchKernelGGL((k_density<R, 16>), dim3(g), dim3(kBlock), 0, s, p, b, k); break;
+    case 1: hipLaunchKernelGGL((k_density<R, 1, NM>), dim3(g), dim3(kBlock), 0, s, p, b, k); break;
+    case 2: hipLaunchKernelGGL((k_density<R, 2, NM>), dim3(g), dim3(kBlock), 0, s, p, b, k); break;
+    case 4: hipLaunchKernelGGL((k_density<R, 4, NM>), dim3(g), dim3(kBlock), 0, s, p, b, k); break;
+    case 8: hipLaunchKernelGGL((k_density<R, 8, NM>), dim3(g), dim3(kBlock), 0, s, p, b, k); break;
+    default: hipLaunchKernelGGL((k_density<R, 16, NM>), dim3(g), dim3(kBlock), 0, s, p, b, k); break;
   }
 }
 
-template <class R>
+template <class R, int NM>
 static void force_lpa(const Params &p, const Buffers &b, int lpa, int32_t k, int32_t mode, hipStream_t s) {
   const unsigned g = (unsigned)(p.ntot * lpa / kBlock);
   switch (lpa) {
-    case 1: hipLaunchKernelGGL((k_force<R, 1>), dim3(g), dim3(kBlock), 0, s, p, b, k, mode); break;
-    case 2: hipLaunchKernelGGL((k_force<R, 2>), dim3(g), dim3(kBlock), 0, s, p, b, k, mode); break;
-    case 4: hipLaunchKernelGGL((k_force<R, 4>), dim3(g), dim3(kBlock), 0, s, p, b, k, mode); break;
-    case 8: hipLaunchKernelGGL((k_force<R, 8>), dim3(g), dim3(kBlock), 0, s, p, b, k, mode); break;
-    default: hipLaunchKernelGGL((k_force<R, 16>), dim3(g), dim3(kBlock), 0, s, p, b, k, mode); break;
+    case 1: hipLaunchKernelGGL((k_force<R, 1, NM>), dim3(g), dim3(kBlock), 0, s, p, b, k, mode); break;
+    case 2: hipLaunchKernelGGL((k_force<R, 2, NM>), dim3(g), dim3(kBlock), 0, s, p, b, k, mode); break;
+    case 4: hipLaunchKernelGGL((k_force<R, 4, NM>), dim3(g), dim3(kBlock), 0, s, p, b, k, mode); break;
+    case 8: hipLaunchKernelGGL((k_force<R, 8, NM>), dim3(g), dim3(kBlock), 0, s, p, b, k, mode); break;
+    default: hipLaunchKernelGGL((k_force<R, 16, NM>), dim3(g), dim3(kBlock), 0, s, p, b, k, mode); break;
   }
 }
 
+static bool is_al76(const Params &p) { return p.n == 7 && p.m == 6; }
+
+template <class R>
+static void build_lpa(const Params &p, const Buffers &b, int lpa, hipStream_t s) {
+  const unsigned g = (unsigned)std::min<int64_t>(p.ntot * KB / kBlock, 4096);
+  switch (lpa) {
+    case 1: hipLaunchKernelGGL((k_build<R, 1>), dim3(g), dim3(kBlock), 0, s, p, b); break;
+    case 2: hipLaunchKernelGGL((k_build<R, 2>), dim3(g), dim3(kBlock), 0, s, p, b); break;
+    case 4: hipLaunchKernelGGL((k_build<R, 4>), dim3(g), dim3(kBlock), 0, s, p, b); break;
+    case 8: hipLaunchKernelGGL((k_build<R, 8>), dim3(g), dim3(kBlock), 0, s, p, b); break;
+    default: hipLaunchKernelGGL((k_build<R, 16>), dim3(g), dim3(kBlock), 0, s, p, b); break;
+  }
+}
+
+void launch_build(const Params &p, const Buffers &b, int precision, int lpa, hipStream_t s) {
+  if (precision) build_lpa<float>(p, b, lpa, s);
+  else build_lpa<double>(p, b, lpa, s);
+}
+
 void launch_density(const Params &p, const Buffers &b, int precision, int lpa, int32_t k, hipStream_t s) {
-  if (precision) density_lpa<float>(p, b, lpa, k, s);
-  else density_lpa<double>(p, b, lpa, k, s);
+  const bool f = is_al76(p);
+  if (precision) f ? density_lpa<float, 1>(p, b, lpa, k, s) : density_lpa<float, 0>(p, b, lpa, k, s);
+  else f ? density_lpa<double, 1>(p, b, lpa, k, s) : density_lpa<double, 0>(p, b, lpa, k, s);
 }
 
 void launch_force(const Params &p, const Buffers &b, int precision, int lpa, int32_t k, int32_t mode,
                   hipStream_t s) {
-  if (precision) force_lpa<float>(p, b, lpa, k, mode, s);
-  else force_lpa<double>(p, b, lpa, k, mode, s);
+  const bool f = is_al76(p);
+  if (precision) f ? force_lpa<float, 1>(p, b, lpa, k, mode, s) : force_lpa<float, 0>(p, b, lpa, k, mode, s);
+  else f ? force_lpa<double, 1>(p, b, lpa, k, mode, s) : force_lpa<double, 0>(p, b, lpa, k, mode, s);
 }
 
 void launch_chunk_stats(const Params &p, const Buffers &b, hipStream_t s) {
+  const int64_t rows = (int64_t)p.n_rep * kSlots;
+  hipLaunchKernelGGL(k_stat_init, dim3((unsigned)std::min<int64_t>((rows * kStat + kBlock - 1) / kBlock, 1024)),
+                     dim3(kBlock), 0, s, b.stat, rows);
   hipLaunchKernelGGL(k_chunk_stats, dim3(tiles(p)), dim3(kBlock), 0, s, p, b);
 }
 
-void launch_bbox(const Params &p, const Buffers &b, hipStream_t s) {
-  hipLaunchKernelGGL(k_bbox, dim3(tiles(p)), dim3(kBlock), 0, s, p, b);
+void launch_copy_back(const Params &p, const Buffers &b, const Buffers &scratch, int precision, hipStream_t s) {
+  if (precision) hipLaunchKernelGGL(k_copy_back<float>, dim3(tiles(p)), dim3(kBlock), 0, s, b, scratch);
+  else hipLaunchKernelGGL(k_copy_back<double>, dim3(tiles(p)), dim3(kBlock), 0, s, b, scratch);
 }
 
 void launch_assign_count(const Params &p, const Buffers &b, int32_t *key, hipStream_t s) {

@@ -34,19 +34,21 @@ enum : int {
   E_ESCAPE = 2,
   E_OVERFLOW = 4,  // Verlet list capacity exceeded
   E_DRIFT = 8,     // an atom drifted beyond the binning margin before a list build
-  E_STATE = 16     // thermostat: T <= 0 or lambda^2 < 0
+  E_STATE = 16,    // thermostat: T <= 0 or lambda^2 < 0
+  E_SKIN = 32      // an atom moved more than half the skin since the list build
 };
 
 // Device-resident control block (one per system).
 struct Control {
   int64_t base;      // absolute step index of the first step in the current chunk
-  int32_t rebuild;   // nonzero: the next density pass rebuilds the Verlet lists
+  int32_t spare;
   int32_t err;       // error bits
   int64_t n_steps;   // steps of the current burst
   int64_t se_block;  // samples per standard-error block (n_steps / 20)
-  int32_t list_builds;
-  int32_t pad0;
+  int64_t ncells;    // cells of all replicas (binning grid of the last sort)
 };
+
+constexpr int kStat = 16;  // u64 entries per statistics row
 
 // Per-replica constants and grid (device memory, read by kernels).
 struct RepInfo {
@@ -81,6 +83,9 @@ struct Params {
   double Vc, dVc, rhoc, drhoc;  // effective shift constants (0 where the mode has none)
   // lists and binning
   double rlist2;       // (rc + skin)^2
+  float rlist2_lo, rlist2_hi;  // FP32 pre-filter band around rlist2 (0.1%)
+  double cull2;        // (rc + skin + margin)^2: cells farther than this hold no list candidate
+  double bin_h;        // binning cell edge: (rlist + 2 margin) / 2, searched with a 5^3 stencil
   double half_skin2;   // (skin/2)^2: displacement that triggers a list rebuild
   double margin2;      // binning margin^2
   double esc2;         // squared escape radius around the replica centre
@@ -92,7 +97,7 @@ struct Params {
   double kb, gpa;
   int64_t ntot;        // padded atoms, all replicas
   int64_t nbr_stride;  // ntot * lanes_per_atom
-  int32_t cap_slots;   // list slots per lane
+  int32_t cap_slots;   // list slots per lane (a multiple of kGroup)
   int32_t lpa;
 };
 
@@ -113,22 +118,34 @@ struct Buffers {
   RepInfo *rep;
   RepAcc *acc;
   unsigned long long *slots;  // [2][n_rep][kSlots][kNQ]
-  unsigned long long *stat;   // [n_rep][kSlots][4] max-reductions (bit patterns of non-negative doubles)
+  unsigned long long *stat;   // [n_rep][kSlots][kStat]: drift^2, v^2, bbox min/max keys, list displacement^2
   double *series;      // [n_rep][series_cap][kSeriesCols]
   int64_t series_cap;
   Control *ctl;
 };
 
+// Verlet-list layout.  Entry e of atom i belongs to lane l = e % lpa at slot
+// s = e / lpa; slots are grouped in fours so that one 16-byte load fetches
+// four indices, and consecutive (atom, lane) pairs are adjacent, so the 64
+// lanes of a wave read 1 KiB contiguously.  stride = ntot * lpa.
+constexpr int kGroup = 4;
+__host__ __device__ inline size_t nbr_index(int64_t i, int e, int lpa, int64_t stride) {
+  const int l = e % lpa, s = e / lpa;
+  return ((size_t)(s / kGroup) * (size_t)stride + (size_t)i * lpa + l) * kGroup + (s % kGroup);
+}
+
 // ---- launch wrappers (kernels.hip) ----
 void launch_burst_begin(const Params &p, const Buffers &b, int n_rep, hipStream_t s);
 void launch_kick_drift(const Params &p, const Buffers &b, int precision, int32_t k, int32_t mode, hipStream_t s);
 void launch_pos4(const Params &p, const Buffers &b, int precision, hipStream_t s);
+void launch_build(const Params &p, const Buffers &b, int precision, int lpa, hipStream_t s);
 void launch_density(const Params &p, const Buffers &b, int precision, int lpa, int32_t k, hipStream_t s);
 void launch_force(const Params &p, const Buffers &b, int precision, int lpa, int32_t k, int32_t mode,
                   hipStream_t s);
 void launch_set_base(const Buffers &b, int64_t base, hipStream_t s);
+void launch_set_ncells(const Buffers &b, int64_t n, hipStream_t s);
 void launch_chunk_stats(const Params &p, const Buffers &b, hipStream_t s);
-void launch_bbox(const Params &p, const Buffers &b, hipStream_t s);
+void launch_copy_back(const Params &p, const Buffers &b, const Buffers &scratch, int precision, hipStream_t s);
 void launch_assign_count(const Params &p, const Buffers &b, int32_t *key, hipStream_t s);
 void launch_scan_cells(const Params &p, const Buffers &b, int32_t *cursor, hipStream_t s);
 void launch_scatter(const Params &p, const Buffers &b, const int32_t *key, int32_t *cursor, int32_t *tmp,

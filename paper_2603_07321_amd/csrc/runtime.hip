@@ -45,7 +45,7 @@ static void dfree(void *p) {
   if (p) (void)hipFree(p);
 }
 
-constexpr int kMaxDims = 64;       // binning grid cells per axis (atoms beyond are clamped into edge cells)
+constexpr int kMaxDims = 128;       // binning grid cells per axis (atoms beyond are clamped into edge cells)
 constexpr int kMaxChunk = 256;     // steps per captured graph
 constexpr int kMinChunk = 4;
 constexpr int kStartChunk = 64;
@@ -93,10 +93,13 @@ struct ptamd_system {
   // host staging
   Control *h_ctl = nullptr;
   unsigned long long *h_stat = nullptr;
+  RepInfo *h_rep = nullptr;
+  bool stats_valid = false;  // h_stat holds the statistics of the current positions
   hipStream_t stream = nullptr;
   hipStream_t cap_stream = nullptr;
   std::map<int, GraphEntry> graphs;
   bool need_sort = true;
+  bool need_build = true;
   bool timing = false;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   double t_sum_ms = 0.0;
@@ -223,17 +226,45 @@ static void upload_reps(ptamd_system *s) {
     d.cell_off = h.cell_off;
     d.ncells = h.ncells;
   }
-  h2d(s, s->B.rep, ri.data(), sizeof(RepInfo) * s->n_rep);
+  // the staging buffer is pinned and only rewritten after a later sync
+  sync(s);
+  std::memcpy(s->h_rep, ri.data(), sizeof(RepInfo) * s->n_rep);
+  HIPCHK(hipMemcpyAsync(s->B.rep, s->h_rep, sizeof(RepInfo) * s->n_rep, hipMemcpyHostToDevice, s->stream));
 }
 
 static void alloc_list(ptamd_system *s, int cap) {
-  cap = (cap + s->lpa - 1) / s->lpa * s->lpa;
+  const int q = s->lpa * kGroup;
+  cap = (cap + q - 1) / q * q;
   dfree(s->B.nbr);
   s->B.nbr = nullptr;
   s->B.nbr = dalloc<int32_t>((size_t)s->ntot * cap);
   s->cap = cap;
   s->P.cap_slots = cap / s->lpa;
   invalidate_graphs(s);
+}
+
+// list radius, rebuild trigger, binning edge and culling radius for the
+// current skin and margin
+static void set_list_geometry(ptamd_system *s) {
+  Params &P = s->P;
+  const double rl = s->sc.rc + s->skin;
+  s->bin_h = 0.5 * (rl + 2.0 * s->margin);  // searched with a 5^3 stencil
+  P.rlist2 = rl * rl;
+  P.rlist2_lo = (float)(rl * rl * (1.0 - 1e-3));
+  P.rlist2_hi = (float)(rl * rl * (1.0 + 1e-3));
+  P.cull2 = (rl + s->margin + 1e-3) * (rl + s->margin + 1e-3);
+  P.bin_h = s->bin_h;
+  // the reference positions of both checks are stored in FP32: keep 1e-3 A
+  // of slack (coordinates up to the 1e4 A escape bound round by < 6e-4 A)
+  P.half_skin2 = (0.5 * s->skin - 1e-3) * (0.5 * s->skin - 1e-3);
+  P.margin2 = (s->margin - 1e-3) * (s->margin - 1e-3);
+}
+
+// 1.3 x the perfect-lattice count within rc + skin, plus slack
+static int list_capacity_guess(const ptamd_system *s) {
+  const double rl = s->sc.rc + s->skin;
+  const double dens = 4.0 / (s->sc.a * s->sc.a * s->sc.a);
+  return (int)(1.3 * dens * 4.18879 * rl * rl * rl) + 32;
 }
 
 static void ensure_series(ptamd_system *s, int64_t rows) {
@@ -260,7 +291,6 @@ static ptamd_system *create_from_hosts(const std::vector<HostState> &hs, const s
     s->md = md;
     s->skin = md.skin;
     s->margin = 1.0;
-    s->bin_h = sc.rc + md.skin + 2.0 * s->margin;
     HIPCHK(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
     HIPCHK(hipEventCreate(&s->ev0));
     HIPCHK(hipEventCreate(&s->ev1));
@@ -304,10 +334,7 @@ static ptamd_system *create_from_hosts(const std::vector<HostState> &hs, const s
     P.n = (int32_t)sc.n; P.m = (int32_t)sc.m;
     shift_consts(sc, sc.eps, sc.n, &P.Vc, &P.dVc);
     shift_consts(sc, 1.0, sc.m, &P.rhoc, &P.drhoc);
-    const double rl = sc.rc + md.skin;
-    P.rlist2 = rl * rl;
-    P.half_skin2 = 0.25 * md.skin * md.skin;
-    P.margin2 = s->margin * s->margin;
+    set_list_geometry(s);
     P.esc2 = 1.0e8;  // 10^4 A around the cube centre
     P.dt = md.dt_fs;
     P.hdt_m = 0.5 * md.dt_fs / (kMassAl * kMvv2e);
@@ -328,7 +355,7 @@ static ptamd_system *create_from_hosts(const std::vector<HostState> &hs, const s
     B.rep = dalloc<RepInfo>(s->n_rep);
     B.acc = dalloc<RepAcc>(s->n_rep);
     B.slots = dalloc<unsigned long long>((size_t)2 * s->n_rep * kSlots * kNQ);
-    B.stat = dalloc<unsigned long long>((size_t)s->n_rep * kSlots * 8);
+    B.stat = dalloc<unsigned long long>((size_t)s->n_rep * kSlots * kStat);
     B.ctl = dalloc<Control>(1);
     s->d_key = dalloc<int32_t>(s->ntot);
     s->d_tmp = dalloc<int32_t>(s->ntot);
@@ -337,12 +364,10 @@ static ptamd_system *create_from_hosts(const std::vector<HostState> &hs, const s
     s->snap_slots = dalloc<unsigned long long>((size_t)2 * s->n_rep * kSlots * kNQ);
     s->snap_acc = dalloc<RepAcc>(s->n_rep);
     HIPCHK(hipHostMalloc((void **)&s->h_ctl, sizeof(Control), 0));
-    HIPCHK(hipHostMalloc((void **)&s->h_stat, sizeof(unsigned long long) * s->n_rep * kSlots * 8, 0));
+    HIPCHK(hipHostMalloc((void **)&s->h_stat, sizeof(unsigned long long) * s->n_rep * kSlots * kStat, 0));
+    HIPCHK(hipHostMalloc((void **)&s->h_rep, sizeof(RepInfo) * s->n_rep, 0));
 
-    // list capacity: 1.3 x the lattice count within rc + skin, plus slack
-    const double dens = 4.0 / (sc.a * sc.a * sc.a);
-    const int cap0 = (int)(1.3 * dens * 4.18879 * rl * rl * rl) + 32;
-    alloc_list(s, cap0);
+    alloc_list(s, list_capacity_guess(s));
     ensure_series(s, 1024);
 
     // host arrays in padded layout
@@ -385,6 +410,7 @@ static ptamd_system *create_from_hosts(const std::vector<HostState> &hs, const s
     dfree(s->snap); dfree(s->snap_slots); dfree(s->snap_acc);
     if (s->h_ctl) (void)hipHostFree(s->h_ctl);
     if (s->h_stat) (void)hipHostFree(s->h_stat);
+    if (s->h_rep) (void)hipHostFree(s->h_rep);
     if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
     if (s->ev0) (void)hipEventDestroy(s->ev0);
     if (s->ev1) (void)hipEventDestroy(s->ev1);
@@ -403,15 +429,22 @@ static double okey_decode(unsigned long long u) {
   return d;
 }
 
+static void read_stats(ptamd_system *s) {
+  const size_t nst = (size_t)s->n_rep * kSlots * kStat;
+  launch_chunk_stats(s->P, s->B, s->stream);
+  check_launch();
+  HIPCHK(hipMemcpyAsync(s->h_stat, s->B.stat, nst * 8, hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(hipMemcpyAsync(s->h_ctl, s->B.ctl, sizeof(Control), hipMemcpyDeviceToHost, s->stream));
+  sync(s);
+  s->stats_valid = true;
+}
+
+// Grid of each replica from the bounding box of the last statistics pass,
+// then a counting sort of the atoms by cell (atoms of a cell by original
+// index), and the permutation of every per-atom array.
 static void sort_system(ptamd_system *s) {
   Buffers &B = s->B;
-  const size_t nst = (size_t)s->n_rep * kSlots * 8;
-  std::vector<unsigned long long> init(nst);
-  for (size_t t = 0; t < nst; ++t) init[t] = ((t % 8) < 3) ? ~0ull : 0ull;
-  h2d(s, B.stat, init.data(), nst * 8);
-  launch_bbox(s->P, B, s->stream);
-  check_launch();
-  d2h(s, s->h_stat, B.stat, nst * 8);
+  if (!s->stats_valid) read_stats(s);
   int64_t cells = 0;
   const double h = s->bin_h;
   for (int r = 0; r < s->n_rep; ++r) {
@@ -419,8 +452,8 @@ static void sort_system(ptamd_system *s) {
     unsigned long long mn[3] = {~0ull, ~0ull, ~0ull}, mx[3] = {0, 0, 0};
     for (int sl = 0; sl < kSlots; ++sl)
       for (int d = 0; d < 3; ++d) {
-        mn[d] = std::min(mn[d], s->h_stat[((size_t)r * kSlots + sl) * 8 + d]);
-        mx[d] = std::max(mx[d], s->h_stat[((size_t)r * kSlots + sl) * 8 + 3 + d]);
+        mn[d] = std::min(mn[d], s->h_stat[((size_t)r * kSlots + sl) * kStat + 2 + d]);
+        mx[d] = std::max(mx[d], s->h_stat[((size_t)r * kSlots + sl) * kStat + 5 + d]);
       }
     rh.inv_h = 1.0 / h;
     int64_t nc = 1;
@@ -437,6 +470,7 @@ static void sort_system(ptamd_system *s) {
     cells += rh.ncells;
   }
   if (cells > s->cells_cap) {
+    sync(s);
     dfree(B.cell_start); dfree(B.cell_count); dfree(s->d_cursor);
     B.cell_start = B.cell_count = s->d_cursor = nullptr;
     const int64_t capc = cells + cells / 4 + 64;
@@ -453,32 +487,27 @@ static void sort_system(ptamd_system *s) {
   launch_scatter(s->P, B, s->d_key, s->d_cursor, s->d_tmp, s->stream);
   launch_cell_sort(s->P, B, s->d_tmp, s->d_perm, cells, s->stream);
   launch_permute(s->P, B, s->S, s->d_perm, s->d_key, s->precision, s->stream);
+  launch_copy_back(s->P, B, s->S, s->precision, s->stream);
+  launch_set_ncells(B, cells, s->stream);
   check_launch();
-  const int64_t N = s->ntot;
-  d2d(s, B.x, s->S.x, 8 * N); d2d(s, B.y, s->S.y, 8 * N); d2d(s, B.z, s->S.z, 8 * N);
-  d2d(s, B.vx, s->S.vx, 8 * N); d2d(s, B.vy, s->S.vy, 8 * N); d2d(s, B.vz, s->S.vz, 8 * N);
-  d2d(s, B.fx, s->S.fx, 8 * N); d2d(s, B.fy, s->S.fy, 8 * N); d2d(s, B.fz, s->S.fz, 8 * N);
-  d2d(s, B.group, s->S.group, N);
-  d2d(s, B.orig, s->S.orig, 4 * N);
-  d2d(s, B.cell, s->S.cell, 4 * N);
-  d2d(s, B.xs, s->S.xs, 4 * N); d2d(s, B.ys, s->S.ys, 4 * N); d2d(s, B.zs, s->S.zs, 4 * N);
-  d2d(s, B.pos4, s->S.pos4, (s->precision ? 16 : 32) * N);
-  const int32_t one = 1;
-  HIPCHK(hipMemcpyAsync(&B.ctl->rebuild, &one, 4, hipMemcpyHostToDevice, s->stream));
-  sync(s);
   s->need_sort = false;
+  s->need_build = true;  // new order: every list is rebuilt
+  s->stats_valid = false;
   s->sorts++;
 }
 
 // ---------------------------------------------------------------------------
 // MD steps
 // ---------------------------------------------------------------------------
-static GraphEntry &get_graph(ptamd_system *s, int K) {
-  auto it = s->graphs.find(K);
+// Graph of K whole steps; with_build puts a Verlet-list build in front.
+static GraphEntry &get_graph(ptamd_system *s, int K, bool with_build) {
+  const int key = 2 * K + (with_build ? 1 : 0);
+  auto it = s->graphs.find(key);
   if (it != s->graphs.end()) return it->second;
   GraphEntry g;
   hipGraph_t graph;
   HIPCHK(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
+  if (with_build) launch_build(s->P, s->B, s->precision, s->lpa, s->cap_stream);
   for (int32_t k = 0; k < K; ++k) {
     launch_kick_drift(s->P, s->B, s->precision, k, 0, s->cap_stream);
     launch_density(s->P, s->B, s->precision, s->lpa, k, s->cap_stream);
@@ -489,7 +518,7 @@ static GraphEntry &get_graph(ptamd_system *s, int K) {
   e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
   (void)hipGraphDestroy(graph);
   if (e != hipSuccess) fail(PTAMD_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
-  return s->graphs[K] = g;
+  return s->graphs[key] = g;
 }
 
 static void snapshot(ptamd_system *s, bool restore) {
@@ -524,15 +553,19 @@ static void raise_err(int err) {
   if (err & E_STATE) fail(PTAMD_ESTATE, "thermostat met T <= 0 or lambda^2 < 0");
 }
 
-// initial forces of a burst (and of the force hook): density + force, forces only
+// Forces at the current positions (burst start, force hook): a Verlet-list
+// build, the density pass and the force pass without the kick.
 static void initial_forces(ptamd_system *s) {
   if (s->need_sort) sort_system(s);
   launch_burst_begin(s->P, s->B, s->n_rep, s->stream);
   launch_set_base(s->B, 0, s->stream);
+  launch_build(s->P, s->B, s->precision, s->lpa, s->stream);
   launch_density(s->P, s->B, s->precision, s->lpa, 0, s->stream);
   launch_force(s->P, s->B, s->precision, s->lpa, 0, 1, s->stream);
   check_launch();
   read_ctl(s);
+  s->list_builds++;
+  s->need_build = false;
   if (s->h_ctl->err & E_OVERFLOW) {
     // grow the lists and try again from the same positions
     alloc_list(s, s->cap * 3 / 2);
@@ -548,25 +581,31 @@ static void initial_forces(ptamd_system *s) {
   raise_err(s->h_ctl->err);
 }
 
-static void chunk_stats(ptamd_system *s, double *drift, double *vmax) {
-  const size_t nst = (size_t)s->n_rep * kSlots * 8;
-  launch_fill_i64(s->B.stat, (int64_t)nst, 0ull, s->stream);
-  launch_chunk_stats(s->P, s->B, s->stream);
-  check_launch();
-  HIPCHK(hipMemcpyAsync(s->h_stat, s->B.stat, nst * 8, hipMemcpyDeviceToHost, s->stream));
-  HIPCHK(hipMemcpyAsync(s->h_ctl, s->B.ctl, sizeof(Control), hipMemcpyDeviceToHost, s->stream));
-  sync(s);
-  double d2 = 0.0, v2 = 0.0;
+struct ChunkStats {
+  double drift = 0.0;  // max distance from the sorted position
+  double vmax = 0.0;   // max speed
+  double ldisp = 0.0;  // max distance from the position at the list build
+};
+
+static ChunkStats chunk_stats(ptamd_system *s) {
+  read_stats(s);
+  double d2 = 0.0, v2 = 0.0, l2 = 0.0;
   for (int r = 0; r < s->n_rep; ++r)
     for (int sl = 0; sl < kSlots; ++sl) {
-      double a, b;
-      std::memcpy(&a, &s->h_stat[((size_t)r * kSlots + sl) * 4], 8);
-      std::memcpy(&b, &s->h_stat[((size_t)r * kSlots + sl) * 4 + 1], 8);
+      const unsigned long long *row = &s->h_stat[((size_t)r * kSlots + sl) * kStat];
+      double a, b, c;
+      std::memcpy(&a, &row[0], 8);
+      std::memcpy(&b, &row[1], 8);
+      std::memcpy(&c, &row[8], 8);
       d2 = std::max(d2, a);
       v2 = std::max(v2, b);
+      l2 = std::max(l2, c);
     }
-  *drift = std::sqrt(d2);
-  *vmax = std::sqrt(v2);
+  ChunkStats cs;
+  cs.drift = std::sqrt(d2);
+  cs.vmax = std::sqrt(v2);
+  cs.ldisp = std::sqrt(l2);
+  return cs;
 }
 
 static void run_burst(ptamd_system *s, int64_t n_steps, ptamd_averages *out) {
@@ -577,27 +616,34 @@ static void run_burst(ptamd_system *s, int64_t n_steps, ptamd_averages *out) {
   } hdr{n_steps, n_steps >= kSEBlocks ? n_steps / kSEBlocks : 0};
   h2d(s, &s->B.ctl->n_steps, &hdr, sizeof(hdr));
   initial_forces(s);
-  double drift = 0.0, vmax = 0.0;
-  chunk_stats(s, &drift, &vmax);
+  ChunkStats st = chunk_stats(s);
   int64_t step = 1;
-  int chunk = kStartChunk;  // the same schedule for every burst: results depend on the inputs only
+  int chunk = kMaxChunk;  // the same schedule for every burst: results depend on the inputs only
   while (step <= n_steps) {
-    // keep every atom within the binning margin of its sorted position until the next check
-    const double vb = std::max(vmax, 1e-4) * s->md.dt_fs * 1.5;
-    if (drift > 0.5 * s->margin) s->need_sort = true;
+    // Chunk length: no atom may move more than half the skin from its
+    // list-build position, nor more than 0.8 of the binning margin from its
+    // sorted position, within the chunk; the per-step bound is 1.5 x the
+    // largest speed times dt.  Sort and list build happen between chunks.
+    const double vb = std::max(st.vmax, 1e-4) * s->md.dt_fs * 1.5;
+    if (st.drift > 0.5 * s->margin) s->need_sort = true;
     if (s->need_sort) {
       sort_system(s);
-      drift = 0.0;
+      st.drift = 0.0;
     }
-    int K = (int)std::min<double>((0.8 * s->margin - drift) / vb, (double)kMaxChunk);
+    const double skin_room = 0.45 * s->skin;
+    if (!s->need_build && st.ldisp + kMinChunk * vb > skin_room) s->need_build = true;
+    const bool build = s->need_build;
+    if (build) st.ldisp = 0.0;
+    int K = (int)std::min<double>({(skin_room - st.ldisp) / vb, (0.8 * s->margin - st.drift) / vb, (double)chunk});
     K = std::max(K, kMinChunk);
-    K = std::min<int64_t>(std::min(K, chunk), n_steps - step + 1);
+    K = (int)std::min<int64_t>(K, n_steps - step + 1);
     snapshot(s, false);
     launch_set_base(s->B, step, s->stream);
     int done = 0;
     if (s->timing) {
       // the chunk's first step is launched directly, its force kernel bracketed
       // by events on the system's stream; the rest of the chunk is a graph
+      if (build) launch_build(s->P, s->B, s->precision, s->lpa, s->stream);
       launch_kick_drift(s->P, s->B, s->precision, 0, 0, s->stream);
       launch_density(s->P, s->B, s->precision, s->lpa, 0, s->stream);
       HIPCHK(hipEventRecord(s->ev0, s->stream));
@@ -607,21 +653,27 @@ static void run_burst(ptamd_system *s, int64_t n_steps, ptamd_averages *out) {
       if (K > 1) launch_set_base(s->B, step + 1, s->stream);
     }
     check_launch();
-    if (K > done) HIPCHK(hipGraphLaunch(get_graph(s, K - done).exec, s->stream));
-    chunk_stats(s, &drift, &vmax);
+    if (K > done) HIPCHK(hipGraphLaunch(get_graph(s, K - done, build && !s->timing).exec, s->stream));
+    st = chunk_stats(s);
     const int err = s->h_ctl->err;
-    if (err & (E_DRIFT | E_OVERFLOW)) {
+    if (err & (E_DRIFT | E_OVERFLOW | E_SKIN)) {
+      // a bound the lists rely on did not hold: re-run the chunk from its start
       snapshot(s, true);
+      s->stats_valid = false;
       if (err & E_OVERFLOW) alloc_list(s, s->cap * 3 / 2);
       clear_err(s);
       s->need_sort = true;
       s->rollbacks++;
       chunk = std::max(kMinChunk, K / 2);
-      drift = 0.0;
+      st = chunk_stats(s);
       if (s->rollbacks > 1000000) fail(PTAMD_EOVERFLOW, "too many roll-backs");
       continue;
     }
     raise_err(err);
+    if (build) {
+      s->list_builds++;
+      s->need_build = false;
+    }
     if (s->timing) {
       float ms = 0.f;
       HIPCHK(hipEventElapsedTime(&ms, s->ev0, s->ev1));
@@ -632,7 +684,6 @@ static void run_burst(ptamd_system *s, int64_t n_steps, ptamd_averages *out) {
     s->steps_total += K;
     chunk = std::min(kMaxChunk, chunk * 2);
   }
-  s->chunk = std::max(kMinChunk, std::min(chunk, kMaxChunk));
   // finalize: lambda of the last step, its sample, the averages
   launch_set_base(s->B, n_steps + 1, s->stream);
   launch_kick_drift(s->P, s->B, s->precision, 0, 1, s->stream);
@@ -683,6 +734,7 @@ static void apply_strains(ptamd_system *s, const double *d_eps) {
   dfree(df);
   upload_reps(s);
   s->need_sort = true;
+  s->stats_valid = false;
 }
 
 // state in/out in original order
@@ -731,6 +783,7 @@ static void set_state(ptamd_system *s, const double *x, const double *y, const d
   check_launch();
   sync(s);
   s->need_sort = true;
+  s->stats_valid = false;
 }
 
 static void compute_forces(ptamd_system *s, double *fx, double *fy, double *fz, double *pe, double *wzz) {
@@ -774,7 +827,7 @@ static void get_neighbors(ptamd_system *s, int64_t *offsets, int32_t *idx, int64
     auto &row = rows[o[i]];
     row.reserve(cnt[i]);
     for (int e = 0; e < cnt[i]; ++e) {
-      const int32_t j = nb[(size_t)(e / s->lpa) * s->P.nbr_stride + (size_t)i * s->lpa + (e % s->lpa)];
+      const int32_t j = nb[nbr_index(i, e, s->lpa, s->P.nbr_stride)];
       row.push_back(o[j]);
     }
     std::sort(row.begin(), row.end());
@@ -819,19 +872,119 @@ static void get_cells(ptamd_system *s, int32_t *cxyz, double *origin, double *in
 
 static void count_pairs(ptamd_system *s, int64_t *pairs, int64_t *entries) {
   if (s->need_sort) initial_forces(s);
-  const size_t nst = (size_t)s->n_rep * kSlots * 8;
+  const size_t nst = (size_t)s->n_rep * kSlots * kStat;
   launch_fill_i64(s->B.stat, (int64_t)nst, 0ull, s->stream);
   launch_count_pairs(s->P, s->B, s->precision, s->stream);
   check_launch();
   d2h(s, s->h_stat, s->B.stat, nst * 8);
+  s->stats_valid = false;
   unsigned long long p = 0, e = 0;
   for (int r = 0; r < s->n_rep; ++r)
     for (int sl = 0; sl < kSlots; ++sl) {
-      p += s->h_stat[((size_t)r * kSlots + sl) * 4];
-      e += s->h_stat[((size_t)r * kSlots + sl) * 4 + 1];
+      p += s->h_stat[((size_t)r * kSlots + sl) * kStat];
+      e += s->h_stat[((size_t)r * kSlots + sl) * kStat + 1];
     }
   *pairs = (int64_t)(p / 2);
   *entries = (int64_t)e;
+}
+
+// ---------------------------------------------------------------------------
+// autotuner: lanes per atom and Verlet skin, by timing probe bursts
+// ---------------------------------------------------------------------------
+static void reconfigure(ptamd_system *s, int lpa, double skin) {
+  sync(s);
+  s->lpa = lpa;
+  s->md.lanes_per_atom = lpa;
+  s->skin = skin;
+  s->md.skin = skin;
+  s->P.lpa = lpa;
+  s->P.nbr_stride = s->ntot * lpa;
+  set_list_geometry(s);
+  alloc_list(s, list_capacity_guess(s));
+  s->need_sort = true;
+}
+
+struct TuneChoice {
+  int lpa;
+  double skin;
+};
+static std::map<std::string, TuneChoice> g_tune_cache;
+
+static void autotune(ptamd_system *s, int64_t probe_steps, int use_cache, int *out_lpa, double *out_skin,
+                     double *out_ms) {
+  if (probe_steps < 10) fail(PTAMD_EINVAL, "probe_steps must be >= 10");
+  char keyb[128];
+  std::snprintf(keyb, sizeof keyb, "n%lld-r%d-p%d-rc%.4f", (long long)s->nreal, s->n_rep, s->precision, s->sc.rc);
+  const std::string key(keyb);
+  if (use_cache) {
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      reconfigure(s, it->second.lpa, it->second.skin);
+      *out_lpa = it->second.lpa;
+      *out_skin = it->second.skin;
+      *out_ms = 0.0;
+      return;
+    }
+  }
+  const int64_t N = s->ntot;
+  // save the state (in the current sorted order, with the order itself)
+  double *save = dalloc<double>((size_t)6 * N);
+  int32_t *save_o = dalloc<int32_t>(N);
+  uint8_t *save_g = dalloc<uint8_t>(N);
+  double *arr[6] = {s->B.x, s->B.y, s->B.z, s->B.vx, s->B.vy, s->B.vz};
+  const int lpa0 = s->lpa;
+  const double skin0 = s->skin;
+  int best_l = lpa0;
+  double best_s = skin0, best_t = 1e300;
+  try {
+    for (int k = 0; k < 6; ++k) d2d(s, save + (size_t)k * N, arr[k], 8 * N);
+    d2d(s, save_o, s->B.orig, 4 * N);
+    d2d(s, save_g, s->B.group, N);
+    sync(s);
+    const int lpas[4] = {2, 4, 8, 16};
+    const double skins[3] = {0.6, 1.0, 1.5};
+    std::vector<ptamd_averages> tmp(s->n_rep);
+    for (int li = 0; li < 4; ++li)
+      for (int si = 0; si < 3; ++si) {
+        reconfigure(s, lpas[li], skins[si]);
+        run_burst(s, 10, tmp.data());  // warm: graphs, sort, lists
+        for (int k = 0; k < 6; ++k) d2d(s, arr[k], save + (size_t)k * N, 8 * N);
+        d2d(s, s->B.orig, save_o, 4 * N);
+        d2d(s, s->B.group, save_g, N);
+        launch_pos4(s->P, s->B, s->precision, s->stream);
+        s->need_sort = true;
+        s->stats_valid = false;
+        sync(s);
+        HIPCHK(hipEventRecord(s->ev0, s->stream));
+        run_burst(s, probe_steps, tmp.data());
+        HIPCHK(hipEventRecord(s->ev1, s->stream));
+        HIPCHK(hipEventSynchronize(s->ev1));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, s->ev0, s->ev1));
+        if (ms < best_t) {
+          best_t = ms;
+          best_l = lpas[li];
+          best_s = skins[si];
+        }
+        for (int k = 0; k < 6; ++k) d2d(s, arr[k], save + (size_t)k * N, 8 * N);
+        d2d(s, s->B.orig, save_o, 4 * N);
+        d2d(s, s->B.group, save_g, N);
+        launch_pos4(s->P, s->B, s->precision, s->stream);
+        s->need_sort = true;
+        s->stats_valid = false;
+        sync(s);
+      }
+  } catch (...) {
+    sync(s);
+    dfree(save); dfree(save_o); dfree(save_g);
+    throw;
+  }
+  dfree(save); dfree(save_o); dfree(save_g);
+  reconfigure(s, best_l, best_s);
+  g_tune_cache[key] = TuneChoice{best_l, best_s};
+  *out_lpa = best_l;
+  *out_skin = best_s;
+  *out_ms = best_t / (double)probe_steps;
 }
 
 static void destroy(ptamd_system *s) {
@@ -845,6 +998,7 @@ static void destroy(ptamd_system *s) {
   dfree(s->snap); dfree(s->snap_slots); dfree(s->snap_acc);
   if (s->h_ctl) (void)hipHostFree(s->h_ctl);
   if (s->h_stat) (void)hipHostFree(s->h_stat);
+  if (s->h_rep) (void)hipHostFree(s->h_rep);
   if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
   if (s->ev0) (void)hipEventDestroy(s->ev0);
   if (s->ev1) (void)hipEventDestroy(s->ev1);
@@ -1059,7 +1213,7 @@ ptamd_status ptamd_get_info(const ptamd_system *sys, ptamd_info *info) {
     info->precision = sys->precision;
     info->lanes_per_atom = sys->lpa;
     info->list_capacity = sys->cap;
-    info->list_builds = sys->h_ctl ? sys->h_ctl->list_builds : 0;
+    info->list_builds = sys->list_builds;
     info->sorts = sys->sorts;
     info->rollbacks = sys->rollbacks;
     info->steps = sys->steps_total;
@@ -1086,6 +1240,19 @@ ptamd_status ptamd_kernel_timing(ptamd_system *sys, double *avg_ms, int64_t *cou
       sys->t_sum_ms = 0.0;
       sys->t_count = 0;
     }
+  });
+}
+
+ptamd_status ptamd_autotune(ptamd_system *sys, int64_t probe_steps, int32_t use_cache, int32_t *lanes_per_atom,
+                            double *skin, double *ms_per_step) {
+  return guard([&] {
+    use_device(sys);
+    int l = 0;
+    double sk = 0.0, ms = 0.0;
+    autotune(sys, probe_steps, use_cache, &l, &sk, &ms);
+    if (lanes_per_atom) *lanes_per_atom = l;
+    if (skin) *skin = sk;
+    if (ms_per_step) *ms_per_step = ms;
   });
 }
 
