@@ -1,20 +1,25 @@
 #!/usr/bin/env python3
 """Throughput of the PTA fast-MD hot path on one MI355X.
 
-One benchmark step = one affine strain increment of the 62,500-atom cube
-(25^3 FCC cells, Sutton-Chen EAM, +1e-4 along z) followed by one 2000-step
-averaging burst (velocity Verlet, Berendsen 100 fs, on-device K/U/sigma_zz
-time averages), in the mixed precision form.  The cube's whole job is 20 such
-steps; the default run times exactly that.
+A benchmark step is one load step of the workload: an affine strain increment
+along z (skipped where the workload holds the strain fixed) followed by one
+averaging burst of velocity-Verlet EAM dynamics with the Berendsen
+thermostat and on-device K / U / sigma_zz time averages.  The default
+workload is the 62,500-atom cube (25^3 FCC cells) in tension, 20 increments
+of +1e-4 each followed by a 2000-step burst, mixed precision; the default run
+times all 20 load steps.  Other workloads (--workload) are the 4,000-atom
+FP64 cube, the 500,000-atom cube in compression, the 64-replica ensemble and
+the 16 uneven cubes.
 
-Prints one JSON line: atom-steps/s of the burst, the roofline of the force
-kernel (timed with HIP events on the library's stream inside the timed
-region), and the FP64 CPU oracle timed on a bounded sample of the same
-workload.
+Prints one JSON line: atom-steps/s of the whole job, the roofline of the force
+kernel (its average duration measured with HIP events on the library's
+stream inside the timed region), the same workload's throughput in FP64 on a
+shorter run, and the FP64 CPU oracle timed on a bounded sample.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -23,29 +28,95 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# algorithmic flop counts per unique pair within rc (FMA = 2 flops): the
-# density term (distance, powers, shift, accumulation) and the force term
-# (distance, powers, derivatives, shifts, pair force, both atoms' force
-# updates, energy, virial)
-FLOPS_DENSITY_PER_PAIR = 17.0
+# Algorithmic counts per unique pair within rc (FMA = 2 flops): the force
+# term (separation 3, r^2 5, 1/r 1, r 1, powers 5, derivatives and shifts 6,
+# pair energy 4, dU/dr 3, pair force 1, both atoms' force updates 12, energy
+# 1, virial 3) is 45 flops; the density term is 17.
 FLOPS_FORCE_PER_PAIR = 45.0
-PEAK_TFLOPS = {1: 157.3, 0: 78.6}  # vector FP32 (mixed) / FP64, MI355X
+FLOPS_DENSITY_PER_PAIR = 17.0
+PEAK_TFLOPS = {1: 157.3, 0: 78.6}  # MI355X vector FP32 (mixed form) / FP64
 HBM_PEAK_GBS = 8000.0
+# Algorithmic HBM bytes per atom-step: density pass reads x (24) and writes
+# B' (8 FP64 / 4 FP32 rounded into the 128-byte mixed figure); force pass
+# reads x (24), B' and v (24), writes v (24) and x (24).
 BYTES_PER_ATOM_STEP = {0: 136.0, 1: 128.0}
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_force_cube25_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2603_07321_amd", "csrc", "kernels.hip")
+
+
+def kernel_source_hash() -> str:
+    with open(KERNEL_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def measured_traffic(workload: str, precision: int, lanes: int):
+    """HBM bytes per force-kernel launch from the committed counter runs, or
+    None when the kernel source or launch shape differs from the profiled one."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernels_hip_sha256_16") != kernel_source_hash():
+        return None
+    if t.get("workload") != workload or t.get("precision") != precision or t.get("lanes_per_atom") != lanes:
+        return None
+    return t.get("bytes_per_launch")
+
+
+def run_workload(P, wl, precision, lanes, steps, warmup, burst, autotune, tune_steps, stream, timing=True):
+    sc = P.sc_params()
+    md = P.md_params(precision=precision, lanes_per_atom=lanes)
+    descs = [P.lattice_desc(nc, T0, seed) for nc, T0, seed in zip(wl.n_cells, wl.T0, wl.seeds)]
+    if len(descs) > 1:
+        sysm = P.System.batch(descs, sc=sc, md=md)
+    else:
+        sysm = P.System.cube(wl.n_cells[0], T0=wl.T0[0], seed=wl.seeds[0], sc=sc, md=md)
+    sysm.set_stream(stream)
+    tune = sysm.autotune(probe_steps=tune_steps) if autotune else None
+    if timing:
+        sysm.kernel_timing(reset=True)  # switches on the force-kernel events
+    strained = any(d != 0.0 for d in wl.d_eps)
+
+    def load_step():
+        if strained:
+            sysm.apply_strain_increments(wl.d_eps)
+        return sysm.run_fast_md(burst)
+
+    for _ in range(warmup):
+        load_step()
+    sysm.kernel_timing(reset=True)
+    info0 = sysm.info()
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    last = None
+    for _ in range(steps):
+        last = load_step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    k_ms, k_count = sysm.kernel_timing(reset=False)
+    info1 = sysm.info()
+    pairs, entries = sysm.count_pairs()
+    return dict(sys=sysm, elapsed=t1 - t0, k_ms=k_ms, k_count=k_count, info0=info0, info1=info1, pairs=pairs,
+                entries=entries, last=last, tune=tune, n_atoms=sysm.n_atoms())
 
 
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20, help="timed load steps (strain increment + burst)")
+    ap.add_argument("--steps", type=int, default=None, help="timed load steps (default: the workload's count)")
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--burst", type=int, default=2000, help="MD steps per burst")
-    ap.add_argument("--precision", type=int, default=1, help="1 mixed (default), 0 FP64")
-    ap.add_argument("--cells", type=int, default=25)
+    ap.add_argument("--workload", default="cube25_tension_mixed")
+    ap.add_argument("--burst", type=int, default=None, help="MD steps per burst (default: the workload's)")
+    ap.add_argument("--precision", type=int, default=None, help="1 mixed, 0 FP64 (default: the workload's)")
     ap.add_argument("--lanes", type=int, default=0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tune-steps", type=int, default=100)
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 side measurement")
+    ap.add_argument("--fp64-steps", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="before the timed region, copy this many MiB device-to-device (a known-size kernel "
@@ -56,8 +127,8 @@ def main() -> int:
     rank = int(os.environ.get("RANK", "0"))
     if args.gpus != 1 or world != 1:
         if rank == 0:
-            print("bench.py measures one GPU only: the hot path here runs on a single MI355X "
-                  "(multi-GPU sharding is a design note, not part of this build); use --gpus 1", file=sys.stderr)
+            print("bench.py measures one GPU only: the hot path runs on a single MI355X here (how it would "
+                  "shard over more GPUs is a design note, not a measured run); use --gpus 1", file=sys.stderr)
         return 2
 
     import torch  # device memory and streams only
@@ -65,14 +136,16 @@ def main() -> int:
     import paper_2603_07321_amd as P
     import synth
 
-    wl = synth.workloads()["cube25_tension_mixed"]
-    nc = args.cells
-    d_eps = wl.d_eps[0]
-    md = P.md_params(precision=args.precision, lanes_per_atom=args.lanes)
-    sysm = P.System.cube(nc, T0=wl.T0[0], seed=wl.seeds[0], md=md)
+    wls = synth.workloads()
+    if args.workload not in wls:
+        print(f"unknown workload {args.workload}; choose from {sorted(wls)}", file=sys.stderr)
+        return 2
+    wl = wls[args.workload]
+    precision = wl.precision if args.precision is None else args.precision
+    steps = wl.increments if args.steps is None else args.steps
+    burst = wl.burst_steps if args.burst is None else args.burst
     stream = torch.cuda.current_stream()
-    sysm.set_stream(stream)
-    n_atoms = sysm.n_atoms()
+
     if args.copy_probe_mb > 0:
         nb = args.copy_probe_mb * (1 << 20) // 4
         src = torch.ones(nb, dtype=torch.float32, device="cuda")
@@ -80,38 +153,15 @@ def main() -> int:
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    tune = None
-    if not args.no_autotune:
-        # warm-up work: probe bursts pick lanes per atom and skin, state restored
-        tune = sysm.autotune(probe_steps=args.tune_steps)
-    sysm.kernel_timing(reset=True)  # switches on the force-kernel events
 
-    for _ in range(args.warmup):
-        sysm.apply_strain_increment(d_eps)
-        sysm.run_fast_md(args.burst)
-    sysm.kernel_timing(reset=True)
-    info0 = sysm.info()
-
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    last = None
-    for _ in range(args.steps):
-        sysm.apply_strain_increment(d_eps)
-        last = sysm.run_fast_md(args.burst)[0]
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    elapsed = t1 - t0
-
-    k_ms, k_count = sysm.kernel_timing(reset=False)
-    info1 = sysm.info()
-    pairs, entries = sysm.count_pairs()  # at the final positions
-    atom_steps = n_atoms * args.burst * args.steps
-    value = atom_steps / elapsed
-    ms_per_step = elapsed / args.steps * 1e3
-
-    flops_launch = FLOPS_FORCE_PER_PAIR * pairs
-    achieved = flops_launch / (k_ms * 1e-3) / 1e12 if k_ms > 0 else None
-    peak = PEAK_TFLOPS[args.precision]
+    r = run_workload(P, wl, precision, args.lanes, steps, args.warmup, burst, not args.no_autotune,
+                     args.tune_steps, stream)
+    n_atoms = r["n_atoms"]
+    value = n_atoms * burst * steps / r["elapsed"]
+    lanes = r["info1"]["lanes_per_atom"]
+    flops_launch = FLOPS_FORCE_PER_PAIR * r["pairs"]
+    achieved = flops_launch / (r["k_ms"] * 1e-3) / 1e12 if r["k_ms"] > 0 else None
+    peak = PEAK_TFLOPS[precision]
     roofline = {
         "kernel": "k_force",
         "bound": "alu",
@@ -119,66 +169,77 @@ def main() -> int:
         "peak": peak,
         "unit": "TFLOP/s",
         "frac": (achieved / peak) if achieved else None,
-        "traffic": None,
-        "kernel_avg_ms": k_ms,
-        "kernel_launches_timed": k_count,
+        "traffic": measured_traffic(args.workload, precision, lanes),
+        "kernel_avg_ms": r["k_ms"],
+        "kernel_launches_timed": r["k_count"],
         "flops_per_launch": flops_launch,
-        "unique_pairs_in_rc": pairs,
-        "list_entries": entries,
+        "unique_pairs_in_rc": r["pairs"],
+        "list_entries": r["entries"],
     }
-    hbm_algo = BYTES_PER_ATOM_STEP[args.precision] * value / 1e9
     out = {
         "metric": "atom-steps/s (EAM force+integrate) and % HBM roofline; FP32-mixed vs FP64",
         "value": value,
         "unit": "atom-steps/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": r["elapsed"] / steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32-pair/f64-state" if args.precision == 1 else "f64",
+        "dtype": "f32-pair/f64-state" if precision == 1 else "f64",
         "data": "synthetic",
         "config": {
-            "workload": f"FCC Al cube {nc}^3 cells ({n_atoms} atoms), Sutton-Chen EAM rc 8.1 A shifted force, "
-                        f"{args.steps} x (affine z strain {d_eps:+g}, {args.burst}-step burst, VV dt 1 fs, "
-                        f"Berendsen 100 fs, 300 K)",
+            "workload": f"{args.workload}: {wl.notes}; Sutton-Chen EAM (eps 0.0033147 eV, a 4.05 A, n 7, m 6, "
+                        f"c 16.399, rc 8.1 A shifted force), velocity Verlet dt 1 fs, Berendsen tau 100 fs",
             "atoms": n_atoms,
-            "burst_steps": args.burst,
-            "precision": "mixed" if args.precision == 1 else "fp64",
-            "lanes_per_atom": info1["lanes_per_atom"],
-            "skin_A": info1["skin"],
-            "autotune": tune,
+            "replicas": len(wl.n_cells),
+            "load_steps": steps,
+            "burst_steps": burst,
+            "precision": "mixed" if precision == 1 else "fp64",
+            "lanes_per_atom": lanes,
+            "skin_A": r["info1"]["skin"],
+            "autotune": r["tune"],
         },
-        "hbm_frac_algorithmic": hbm_algo / HBM_PEAK_GBS,
+        "hbm_frac_algorithmic": BYTES_PER_ATOM_STEP[precision] * value / 1e9 / HBM_PEAK_GBS,
         "roofline": roofline,
         "run_stats": {
-            "list_builds": info1["list_builds"] - info0["list_builds"],
-            "sorts": info1["sorts"] - info0["sorts"],
-            "rollbacks": info1["rollbacks"] - info0["rollbacks"],
-            "last_burst": last,
+            "list_builds": r["info1"]["list_builds"] - r["info0"]["list_builds"],
+            "sorts": r["info1"]["sorts"] - r["info0"]["sorts"],
+            "rollbacks": r["info1"]["rollbacks"] - r["info0"]["rollbacks"],
+            "last_burst_replica0": r["last"][0] if r["last"] else None,
         },
     }
+    r["sys"].close()
+
+    if precision == 1 and not args.no_fp64:
+        n64 = min(args.fp64_steps, steps)
+        f = run_workload(P, wl, 0, 0, n64, 1, burst, not args.no_autotune, args.tune_steps, stream, timing=False)
+        v64 = n_atoms * burst * n64 / f["elapsed"]
+        out["fp64"] = {"value": v64, "unit": "atom-steps/s", "steps": n64, "mixed_over_fp64": value / v64,
+                       "lanes_per_atom": f["info1"]["lanes_per_atom"], "skin_A": f["info1"]["skin"]}
+        f["sys"].close()
 
     if not args.no_cpu_baseline:
         import oracle as O
+        nc = wl.n_cells[0]
         st = O.create_cube(nc, wl.T0[0], wl.seeds[0])
-        O.apply_strain(st, d_eps)
+        if wl.d_eps[0] != 0.0:
+            O.apply_strain(st, wl.d_eps[0])
         c0 = time.perf_counter()
-        O.run_burst(st, O.sc_params(), O.md_params(), args.cpu_steps)
+        O.run_burst(st, O.sc_params(), O.md_params(T0=wl.T0[0]), args.cpu_steps)
         c1 = time.perf_counter()
+        n0 = 4 * nc ** 3
         out["cpu_baseline"] = {
-            "value": n_atoms * args.cpu_steps / (c1 - c0),
+            "value": n0 * args.cpu_steps / (c1 - c0),
             "unit": "atom-steps/s",
             "cores": O.num_threads(),
             "kind": "oracle",
-            "sample": f"one strain increment + {args.cpu_steps}-step burst of the same {n_atoms}-atom cube "
-                      f"(FP64, all-pairs loops, includes the burst-start force evaluation)",
+            "sample": f"the first replica's cube ({n0} atoms): one load step with a {args.cpu_steps}-step burst "
+                      f"(FP64, all-pairs loops, burst-start force evaluation included)",
             "seconds": c1 - c0,
         }
     print(json.dumps(out))
-    sysm.close()
     return 0
 
 

@@ -878,6 +878,37 @@ __global__ __launch_bounds__(kBlock) void k_permute(Buffers b, Buffers sc, const
   reinterpret_cast<V4 *>(sc.pos4)[i] = v;
 }
 
+// state copy for roll-back: restore == 0 saves into the snapshot, 1 restores
+__global__ __launch_bounds__(kBlock) void k_snapshot(Buffers b, double *snap, unsigned long long *snap_slots,
+                                                     double *snap_acc, int restore, int64_t ntot, int64_t nslots,
+                                                     int64_t nacc) {
+  double *arr[9] = {b.x, b.y, b.z, b.vx, b.vy, b.vz, b.fx, b.fy, b.fz};
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < ntot; t += stride) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      if (restore) arr[k][t] = snap[k * ntot + t];
+      else snap[k * ntot + t] = arr[k][t];
+    }
+  }
+  double *acc = reinterpret_cast<double *>(b.acc);
+  for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < nslots; t += stride) {
+    if (restore) b.slots[t] = snap_slots[t];
+    else snap_slots[t] = b.slots[t];
+  }
+  for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < nacc; t += stride) {
+    if (restore) acc[t] = snap_acc[t];
+    else snap_acc[t] = acc[t];
+  }
+}
+
+void launch_snapshot(const Buffers &b, double *snap, unsigned long long *snap_slots, double *snap_acc, int restore,
+                     int64_t ntot, int64_t nslots, int64_t nacc, hipStream_t s) {
+  const unsigned g = (unsigned)std::min<int64_t>((ntot + kBlock - 1) / kBlock, 2048);
+  hipLaunchKernelGGL(k_snapshot, dim3(g), dim3(kBlock), 0, s, b, snap, snap_slots, snap_acc, restore, ntot, nslots,
+                     nacc);
+}
+
 // copy the permuted arrays back into the primary buffers (one launch)
 template <class R>
 __global__ __launch_bounds__(kBlock) void k_copy_back(Buffers b, Buffers sc) {

@@ -145,6 +145,8 @@ void launch_force(const Params &p, const Buffers &b, int precision, int lpa, int
 void launch_set_base(const Buffers &b, int64_t base, hipStream_t s);
 void launch_set_ncells(const Buffers &b, int64_t n, hipStream_t s);
 void launch_chunk_stats(const Params &p, const Buffers &b, hipStream_t s);
+void launch_snapshot(const Buffers &b, double *snap, unsigned long long *snap_slots, double *snap_acc, int restore,
+                     int64_t ntot, int64_t nslots, int64_t nacc, hipStream_t s);
 void launch_copy_back(const Params &p, const Buffers &b, const Buffers &scratch, int precision, hipStream_t s);
 void launch_assign_count(const Params &p, const Buffers &b, int32_t *key, hipStream_t s);
 void launch_scan_cells(const Params &p, const Buffers &b, int32_t *cursor, hipStream_t s);

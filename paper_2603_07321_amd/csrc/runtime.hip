@@ -59,6 +59,7 @@ struct RepHost {
   double inv_h = 0;
   int dims[3] = {1, 1, 1};
   int64_t cell_off = 0, ncells = 0;
+  double nom_lo[3] = {0, 0, 0}, nom_hi[3] = {0, 0, 0};  // extent of the sample at creation (strain 0)
 };
 
 struct GraphEntry {
@@ -320,7 +321,11 @@ static ptamd_system *create_from_hosts(const std::vector<HostState> &hs, const s
         }
       }
       if (h.nmob < 2) fail(PTAMD_EINVAL, "a replica needs at least two mobile atoms");
-      for (int k = 0; k < 3; ++k) h.center[k] = 0.5 * (lo[k] + hi[k]);
+      for (int k = 0; k < 3; ++k) {
+        h.center[k] = 0.5 * (lo[k] + hi[k]);
+        h.nom_lo[k] = lo[k];
+        h.nom_hi[k] = hi[k];
+      }
       off = h.aend;
       obase += n;
       s->nreal += n;
@@ -458,8 +463,18 @@ static void sort_system(ptamd_system *s) {
     rh.inv_h = 1.0 / h;
     int64_t nc = 1;
     for (int d = 0; d < 3; ++d) {
-      const double lo = okey_decode(mn[d]), hi = okey_decode(mx[d]);
+      double lo = okey_decode(mn[d]), hi = okey_decode(mx[d]);
       if (!std::isfinite(lo) || !std::isfinite(hi)) fail(PTAMD_ENONFINITE, "non-finite position at sort");
+      // The grid spans the atoms, but no more than the sample's nominal
+      // extent (z follows the applied strain) plus a pad: atoms that
+      // evaporated farther away are clamped into the edge bins, which keeps
+      // the search correct and the grid small.
+      const double f = (d == 2) ? (1.0 + rh.strain) : 1.0;
+      const double nlo = rh.nom_lo[d] * f, nhi = rh.nom_hi[d] * f;
+      const double pad = std::max(2.0 * h, 0.25 * (nhi - nlo));
+      lo = std::max(lo, nlo - pad);
+      hi = std::min(hi, nhi + pad);
+      if (hi < lo) hi = lo;
       rh.origin[d] = lo - 0.5 * h;
       const double span = std::floor((hi - rh.origin[d]) * rh.inv_h) + 1.0;
       rh.dims[d] = (int)std::min<double>(std::max(span, 1.0), (double)kMaxDims);
@@ -521,22 +536,15 @@ static GraphEntry &get_graph(ptamd_system *s, int K, bool with_build) {
   return s->graphs[key] = g;
 }
 
+// Copy of the dynamic state (positions, velocities, forces, the reduction
+// slots and the burst accumulators) taken before each chunk, so that a chunk
+// can be re-run when a bound it relies on fails.  One kernel either way.
 static void snapshot(ptamd_system *s, bool restore) {
-  const int64_t N = s->ntot;
-  double *arr[9] = {s->B.x, s->B.y, s->B.z, s->B.vx, s->B.vy, s->B.vz, s->B.fx, s->B.fy, s->B.fz};
-  const size_t nsl = (size_t)2 * s->n_rep * kSlots * kNQ * 8;
-  for (int k = 0; k < 9; ++k) {
-    if (restore) d2d(s, arr[k], s->snap + (size_t)k * N, 8 * N);
-    else d2d(s, s->snap + (size_t)k * N, arr[k], 8 * N);
-  }
-  if (restore) {
-    d2d(s, s->B.slots, s->snap_slots, nsl);
-    d2d(s, s->B.acc, s->snap_acc, sizeof(RepAcc) * s->n_rep);
-    launch_pos4(s->P, s->B, s->precision, s->stream);
-  } else {
-    d2d(s, s->snap_slots, s->B.slots, nsl);
-    d2d(s, s->snap_acc, s->B.acc, sizeof(RepAcc) * s->n_rep);
-  }
+  launch_snapshot(s->B, s->snap, s->snap_slots, reinterpret_cast<double *>(s->snap_acc), restore ? 1 : 0,
+                  s->ntot, (int64_t)2 * s->n_rep * kSlots * kNQ,
+                  (int64_t)s->n_rep * (int64_t)(sizeof(RepAcc) / sizeof(double)), s->stream);
+  if (restore) launch_pos4(s->P, s->B, s->precision, s->stream);
+  check_launch();
 }
 
 static void read_ctl(ptamd_system *s) { d2h(s, s->h_ctl, s->B.ctl, sizeof(Control)); }
