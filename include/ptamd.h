@@ -189,9 +189,16 @@ ptamd_status ptamd_get_info(const ptamd_system *sys, ptamd_info *info);
 /* Orders all later device work on stream (a hipStream_t, e.g. torch's
  * current stream on ROCm).  NULL selects the null stream. */
 ptamd_status ptamd_set_stream(ptamd_system *sys, void *hip_stream);
-/* Average duration in ms of the force kernel over the launches it timed with
- * HIP events on the system's stream since the last reset, and the count. */
-ptamd_status ptamd_kernel_timing(ptamd_system *sys, double *avg_ms, int64_t *count, int32_t reset);
+/* Timing of the force kernel.  The first call switches timing on; from then
+ * on the first step of every burst chunk launches the force kernel directly
+ * (the rest of the chunk stays a graph): each block stamps the device wall
+ * clock at its start and end, and the launch's span (earliest start to latest
+ * end) is averaged into avg_ms; the same launches are also bracketed by HIP
+ * events on the system's stream (avg_event_ms, which also holds the dispatch
+ * latency of a direct launch).  count = launches timed since the last reset.
+ * Outputs may be NULL. */
+ptamd_status ptamd_kernel_timing(ptamd_system *sys, double *avg_ms, double *avg_event_ms, int64_t *count,
+                                 int32_t reset);
 /* Autotuner: times probe bursts of probe_steps (>= 10) steps from the
  * current state for lanes per atom in {2, 4, 8, 16} and Verlet skin in
  * {0.6, 1.0, 1.5} A, keeps the fastest, and restores the state exactly

@@ -97,7 +97,7 @@ SIGNATURES = {
     "ptamd_get_series": [_SYS, C.c_int32, _P, C.c_int64],
     "ptamd_get_info": [_SYS, C.POINTER(Info)],
     "ptamd_set_stream": [_SYS, C.c_void_p],
-    "ptamd_kernel_timing": [_SYS, _D, C.POINTER(C.c_int64), C.c_int32],
+    "ptamd_kernel_timing": [_SYS, _D, _D, C.POINTER(C.c_int64), C.c_int32],
     "ptamd_autotune": [_SYS, C.c_int64, C.c_int32, C.POINTER(C.c_int32), _D, _D],
     "ptamd_count_pairs": [_SYS, C.POINTER(C.c_int64), C.POINTER(C.c_int64)],
     "ptamd_last_error": [],
@@ -268,9 +268,11 @@ def set_stream(sys: int, stream) -> None:
 
 
 def kernel_timing(sys: int, reset: bool = False):
-    ms, cnt = C.c_double(), C.c_int64()
-    _check(_lib.ptamd_kernel_timing(sys, C.byref(ms), C.byref(cnt), int(reset)))
-    return ms.value, cnt.value
+    """(average force-kernel span in ms from in-kernel device clock stamps,
+    average of the same launches bracketed by HIP events in ms, count)."""
+    ms, ev, cnt = C.c_double(), C.c_double(), C.c_int64()
+    _check(_lib.ptamd_kernel_timing(sys, C.byref(ms), C.byref(ev), C.byref(cnt), int(reset)))
+    return ms.value, ev.value, cnt.value
 
 
 def autotune(sys: int, probe_steps: int = 100, use_cache: bool = True) -> dict:

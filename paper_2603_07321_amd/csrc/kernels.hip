@@ -549,6 +549,7 @@ __global__ __launch_bounds__(kBlock) void k_density(Params p, Buffers b, int32_t
 template <class R, int LPA, int NM>
 __global__ __launch_bounds__(kBlock) void k_force(Params p, Buffers b, int32_t k, int32_t mode) {
   using V4 = typename V4T<R>::T;
+  const unsigned long long t_begin = p.ktime ? wall_clock64() : 0ull;
   const int64_t gt = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int64_t i = gt / LPA;
   const int lane = (int)(gt & (LPA - 1));
@@ -640,6 +641,12 @@ __global__ __launch_bounds__(kBlock) void k_force(Params p, Buffers b, int32_t k
   }
   block_atoms_add<kNQ, kBlock / LPA>(q, lane == 0, threadIdx.x / LPA,
                                      slot_row(b, p.n_rep, par, r, blockIdx.x & (kSlots - 1)));
+  if (p.ktime && threadIdx.x == 0) {
+    // span of this block on the device wall clock (the host takes the
+    // earliest start and the latest end over all blocks)
+    b.ktime[2 * (size_t)blockIdx.x] = t_begin;
+    b.ktime[2 * (size_t)blockIdx.x + 1] = wall_clock64();
+  }
 
 }
 

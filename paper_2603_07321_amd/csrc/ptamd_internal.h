@@ -99,6 +99,8 @@ struct Params {
   int64_t nbr_stride;  // ntot * lanes_per_atom
   int32_t cap_slots;   // list slots per lane (a multiple of kGroup)
   int32_t lpa;
+  int32_t ktime;       // nonzero: the force kernel stamps per-block start/end times into Buffers::ktime
+  int32_t pad2;
 };
 
 // Device buffers (pointers), passed by value.
@@ -120,6 +122,7 @@ struct Buffers {
   unsigned long long *slots;  // [2][n_rep][kSlots][kNQ]
   unsigned long long *stat;   // [n_rep][kSlots][kStat]: drift^2, v^2, bbox min/max keys, list displacement^2
   double *series;      // [n_rep][series_cap][kSeriesCols]
+  unsigned long long *ktime;  // [blocks][2]: device wall-clock at block start and end (timed launches)
   int64_t series_cap;
   Control *ctl;
 };

@@ -102,6 +102,8 @@ struct ptamd_system {
   bool need_sort = true;
   bool need_build = true;
   bool timing = false;
+  double t_ev_ms = 0.0;   // the same launches bracketed by HIP events (includes dispatch latency)
+  double wall_khz = 1e5;  // device wall-clock rate
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   double t_sum_ms = 0.0;
   int64_t t_count = 0;
@@ -203,7 +205,7 @@ static void alloc_buffers(Buffers &b, int64_t ntot, int precision, bool primary)
 static void free_buffers(Buffers &b) {
   void *ptrs[] = {b.x, b.y, b.z, b.vx, b.vy, b.vz, b.fx, b.fy, b.fz, b.pos4, b.group, b.orig, b.cell,
                   b.xs, b.ys, b.zs, b.xr, b.yr, b.zr, b.nbr, b.ncount, b.cell_start, b.cell_count,
-                  b.blk_rep, b.rep, b.acc, b.slots, b.stat, b.series, b.ctl};
+                  b.blk_rep, b.rep, b.acc, b.slots, b.stat, b.series, b.ctl, b.ktime};
   for (void *p : ptrs) dfree(p);
   b = Buffers{};
 }
@@ -295,6 +297,11 @@ static ptamd_system *create_from_hosts(const std::vector<HostState> &hs, const s
     HIPCHK(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
     HIPCHK(hipEventCreate(&s->ev0));
     HIPCHK(hipEventCreate(&s->ev1));
+    {
+      int khz = 0;
+      HIPCHK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, s->device));
+      if (khz > 0) s->wall_khz = (double)khz;
+    }
     s->stream = nullptr;
     // layout: each replica padded to whole tiles
     int64_t off = 0, obase = 0;
@@ -362,6 +369,7 @@ static ptamd_system *create_from_hosts(const std::vector<HostState> &hs, const s
     B.slots = dalloc<unsigned long long>((size_t)2 * s->n_rep * kSlots * kNQ);
     B.stat = dalloc<unsigned long long>((size_t)s->n_rep * kSlots * kStat);
     B.ctl = dalloc<Control>(1);
+    B.ktime = dalloc<unsigned long long>((size_t)2 * (s->ntot * 16 / kBlock + 1));
     s->d_key = dalloc<int32_t>(s->ntot);
     s->d_tmp = dalloc<int32_t>(s->ntot);
     s->d_perm = dalloc<int32_t>(s->ntot);
@@ -654,8 +662,10 @@ static void run_burst(ptamd_system *s, int64_t n_steps, ptamd_averages *out) {
       if (build) launch_build(s->P, s->B, s->precision, s->lpa, s->stream);
       launch_kick_drift(s->P, s->B, s->precision, 0, 0, s->stream);
       launch_density(s->P, s->B, s->precision, s->lpa, 0, s->stream);
+      Params pt = s->P;
+      pt.ktime = 1;
       HIPCHK(hipEventRecord(s->ev0, s->stream));
-      launch_force(s->P, s->B, s->precision, s->lpa, 0, 0, s->stream);
+      launch_force(pt, s->B, s->precision, s->lpa, 0, 0, s->stream);
       HIPCHK(hipEventRecord(s->ev1, s->stream));
       done = 1;
       if (K > 1) launch_set_base(s->B, step + 1, s->stream);
@@ -685,7 +695,16 @@ static void run_burst(ptamd_system *s, int64_t n_steps, ptamd_averages *out) {
     if (s->timing) {
       float ms = 0.f;
       HIPCHK(hipEventElapsedTime(&ms, s->ev0, s->ev1));
-      s->t_sum_ms += ms;
+      s->t_ev_ms += ms;
+      const int64_t nb = s->ntot * s->lpa / kBlock;
+      std::vector<unsigned long long> kt((size_t)2 * nb);
+      d2h(s, kt.data(), s->B.ktime, 16 * (size_t)nb);
+      unsigned long long t0 = ~0ull, t1 = 0ull;
+      for (int64_t q = 0; q < nb; ++q) {
+        t0 = std::min(t0, kt[2 * q]);
+        t1 = std::max(t1, kt[2 * q + 1]);
+      }
+      s->t_sum_ms += (double)(t1 - t0) / s->wall_khz;
       s->t_count++;
     }
     step += K;
@@ -1238,14 +1257,17 @@ ptamd_status ptamd_set_stream(ptamd_system *sys, void *hip_stream) {
   });
 }
 
-ptamd_status ptamd_kernel_timing(ptamd_system *sys, double *avg_ms, int64_t *count, int32_t reset) {
+ptamd_status ptamd_kernel_timing(ptamd_system *sys, double *avg_ms, double *avg_event_ms, int64_t *count,
+                                 int32_t reset) {
   return guard([&] {
     if (!sys) fail(PTAMD_EINVAL, "NULL system");
     sys->timing = true;
     if (avg_ms) *avg_ms = sys->t_count ? sys->t_sum_ms / (double)sys->t_count : 0.0;
+    if (avg_event_ms) *avg_event_ms = sys->t_count ? sys->t_ev_ms / (double)sys->t_count : 0.0;
     if (count) *count = sys->t_count;
     if (reset) {
       sys->t_sum_ms = 0.0;
+      sys->t_ev_ms = 0.0;
       sys->t_count = 0;
     }
   });
