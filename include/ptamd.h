@@ -158,6 +158,105 @@ ptamd_status ptamd_apply_strain_increments(ptamd_system *sys, const double *d_ep
  * recomputed from the positions at the start.  out has n_replicas entries. */
 ptamd_status ptamd_run_fast_md(ptamd_system *sys, int64_t n_steps, ptamd_averages *out);
 
+/* Convergence test of the running time averages (App. A, Eq. (R_m_conv)).
+ * With R(i) the running average of a state function over samples 1..i, a
+ * replica's burst ends at the first checkpoint i = j*lag, j >= 2, at which
+ * every tested function f satisfies
+ *     |R(i) - R(i-lag)| / max(|R(i)|, floor[f]) < tol[f].
+ * Functions in the order K, U, sigma_zz, T_z; tol[f] <= 0 leaves f out (at
+ * least one must be tested); floor[f] >= 0 (0 gives the plain relative
+ * error of the appendix).  n_max is N_max: a replica not converged after
+ * n_max samples stops there.  Table 1 gives tol 0.05 for K, U and the
+ * reaction stress and N_max = 50000; the paper does not give the lag. */
+typedef struct {
+    int64_t lag;     /* >= 1 */
+    int64_t n_max;   /* >= 2 * lag */
+    double tol[4];
+    double floor[4];
+} ptamd_conv_params;
+
+/* One averaging burst per replica whose length the convergence test sets
+ * (Sec. 2.2 Step 1: N_t is the number of steps the running averages need to
+ * converge).  Each replica stops at its own N_s, frozen from then on (its
+ * final state is the state after sample N_s, the x^conv that Sec. 2.2 Step 4
+ * carries to the next run), while the others go on in the same launches.
+ * out[r] averages samples 1..N_s (n_samples = N_s); its standard errors come
+ * from the complete batches of a batch-means scheme whose batches start at
+ * max(1, lag/10) samples and double in length whenever 20 are full (NaN with
+ * fewer than 2).  n_conv[r] = N_s, or 0 if replica r had not converged after
+ * n_max samples (out[r] then averages all n_max).  Both arrays have
+ * n_replicas entries. */
+ptamd_status ptamd_run_until_converged(ptamd_system *sys, const ptamd_conv_params *conv, ptamd_averages *out,
+                                       int64_t *n_conv);
+
+/* ---- the PTA slow-time driver (Sec. 2.2 Steps 1-4, Sec. 2.4.2) ----
+ * One slow step t -> t+h takes three converged runs (ptamd_run_until_converged)
+ * at the strains of slow times t+h-Delta, t+h-Delta/2 and t+h, each started
+ * from the state the run before it left (Eq. (x_guess_step3)), so one
+ * trajectory per replica carries through the whole sequence; between the
+ * runs the load moves by affine strain increments.  Slow time is measured by
+ * the applied strain: the first run of ptamd_pta_start is at the current
+ * strain (slow time -Delta), and a jump h advances the strain by d_eps_h.
+ * The slow variables v are the averaged K, U, sigma_zz and T_z (the paper's
+ * are K, U and the reaction stress).  Per state function f:
+ *   Step 1, Eq. (dvdt_algo): dv/dt = (R_t - R_{t-Delta}) / Delta
+ *   Step 2, Eq. (pta_pred):  v_pred(t+h) = v(t) + h dv/dt
+ *   Step 3, Eq. (simp):      v_d(t+h) = (R_{t+h-Delta} + 4 R_{t+h-Delta/2} + R_{t+h}) / 6
+ *           Eq. (rel_err):   e_v = |(v_pred - v_d) / v_d|
+ *   match (status 0) if e_v < tol_v[f]: v(t+h) = v_pred; otherwise the jump
+ *   test of Eq. (jump_err), e1 = |(R_{t+h} - R_t)/R_t|, e2 = |(R_t - R_{t-h})/R_{t-h}|,
+ *   flags a jump (status 1) if |e1/e2 - 1| >= tol_j[f], or if e1 >= tol_j[f]
+ *   when a jump was flagged at t or there is no R_{t-h} yet (the first jump);
+ *   with a jump, or with neither (status 2), v(t+h) = v_d.
+ * All of it is FP64 host arithmetic exactly as written (IEEE: x/0 = inf,
+ * comparisons with NaN are false).  Table 1: Delta = h/5; tol_v 1% K, 5% U,
+ * 1% reaction; tol_j 8% K, 1% U, 5% reaction. */
+typedef struct {
+    double d_eps_h;             /* strain advanced per slow jump h (strain rate x h), |.| < 0.05 */
+    double delta_over_h;        /* Delta / h, in (0, 1] */
+    ptamd_conv_params conv;     /* how every running average is converged */
+    double tol_v[4];            /* Eq. (rel_err) tolerance: K, U, sigma_zz, T_z */
+    double tol_j[4];            /* Eq. (jump_err) tolerance */
+} ptamd_pta_params;
+
+/* Slow history of one replica, carried from one jump to the next (plain
+ * data: the caller may store and restore it). */
+typedef struct {
+    double strain;              /* strain at slow time t */
+    double R_tmd[4];            /* R(t - Delta) */
+    double R_tmh[4];            /* R(t - Delta/2) */
+    double R_t[4];              /* R(t) */
+    double R_prev[4];           /* R(t - h), meaningful once n_jumps >= 1 */
+    double v[4];                /* slow variables v(t) */
+    int32_t jump_at_t[4];       /* a jump of the measure was flagged at t */
+    int64_t n_jumps;            /* jumps taken since ptamd_pta_start */
+} ptamd_pta_state;
+
+/* What one slow step (or the start) did, per replica. */
+typedef struct {
+    double strain[3];           /* strains of the three runs */
+    double R[3][4];             /* their converged running averages */
+    int64_t n_steps[3];         /* N_s of each run (0: stopped at n_max unconverged) */
+    double v_pred[4], v_d[4], v[4];
+    double e_v[4], e1[4], e2[4];
+    int32_t status[4];          /* 0 match, 1 jump, 2 neither, -1 start (no test) */
+} ptamd_pta_record;
+
+/* Slow time 0: runs at the current strain and after two increments of
+ * Delta/2 (Sec. 2.4.2 steps 1-3); v(0) is their Simpson value.  state and
+ * rec have n_replicas entries. */
+ptamd_status ptamd_pta_start(ptamd_system *sys, const ptamd_pta_params *prm, ptamd_pta_state *state,
+                             ptamd_pta_record *rec);
+/* One slow step t -> t+h for every replica (Sec. 2.2 Steps 1-4). */
+ptamd_status ptamd_pta_jump(ptamd_system *sys, const ptamd_pta_params *prm, ptamd_pta_state *state,
+                            ptamd_pta_record *rec);
+/* The arithmetic of one slow step alone (no device work): advances one
+ * replica's state from t to t+h given the converged averages R[3][4] of the
+ * three runs, their strains and N_s.  Host only; usable without a GPU. */
+ptamd_status ptamd_pta_update(const ptamd_pta_params *prm, ptamd_pta_state *state, const double *R /* 3x4 */,
+                              const double *strains /* 3 */, const int64_t *n_steps /* 3 */,
+                              ptamd_pta_record *rec);
+
 /* ---- state in and out (original order, all replicas concatenated) ---- */
 ptamd_status ptamd_get_num_atoms(const ptamd_system *sys, int64_t *n);
 ptamd_status ptamd_get_state(ptamd_system *sys, double *x, double *y, double *z, double *vx, double *vy,

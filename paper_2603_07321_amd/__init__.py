@@ -62,6 +62,42 @@ class Averages(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class ConvParams(C.Structure):
+    _fields_ = [("lag", C.c_int64), ("n_max", C.c_int64), ("tol", C.c_double * 4), ("floor", C.c_double * 4)]
+
+
+class PTAParams(C.Structure):
+    _fields_ = [("d_eps_h", C.c_double), ("delta_over_h", C.c_double), ("conv", ConvParams),
+                ("tol_v", C.c_double * 4), ("tol_j", C.c_double * 4)]
+
+
+class PTAState(C.Structure):
+    _fields_ = [("strain", C.c_double), ("R_tmd", C.c_double * 4), ("R_tmh", C.c_double * 4),
+                ("R_t", C.c_double * 4), ("R_prev", C.c_double * 4), ("v", C.c_double * 4),
+                ("jump_at_t", C.c_int32 * 4), ("n_jumps", C.c_int64)]
+
+    def as_dict(self):
+        return _struct_dict(self)
+
+
+class PTARecord(C.Structure):
+    _fields_ = [("strain", C.c_double * 3), ("R", (C.c_double * 4) * 3), ("n_steps", C.c_int64 * 3),
+                ("v_pred", C.c_double * 4), ("v_d", C.c_double * 4), ("v", C.c_double * 4),
+                ("e_v", C.c_double * 4), ("e1", C.c_double * 4), ("e2", C.c_double * 4),
+                ("status", C.c_int32 * 4)]
+
+    def as_dict(self):
+        return _struct_dict(self)
+
+
+def _struct_dict(st) -> dict:
+    out = {}
+    for k, _ in st._fields_:
+        v = getattr(st, k)
+        out[k] = np.array([list(r) for r in v]) if k == "R" else (np.array(list(v)) if hasattr(v, "_length_") else v)
+    return out
+
+
 class Info(C.Structure):
     _fields_ = [("n_atoms", C.c_int64), ("n_replicas", C.c_int32), ("precision", C.c_int32),
                 ("lanes_per_atom", C.c_int32), ("list_capacity", C.c_int32), ("list_builds", C.c_int64),
@@ -87,6 +123,10 @@ SIGNATURES = {
     "ptamd_apply_strain_increment": [_SYS, C.c_double],
     "ptamd_apply_strain_increments": [_SYS, _P],
     "ptamd_run_fast_md": [_SYS, C.c_int64, C.POINTER(Averages)],
+    "ptamd_run_until_converged": [_SYS, C.POINTER(ConvParams), C.POINTER(Averages), _P],
+    "ptamd_pta_start": [_SYS, C.POINTER(PTAParams), C.POINTER(PTAState), C.POINTER(PTARecord)],
+    "ptamd_pta_jump": [_SYS, C.POINTER(PTAParams), C.POINTER(PTAState), C.POINTER(PTARecord)],
+    "ptamd_pta_update": [C.POINTER(PTAParams), C.POINTER(PTAState), _P, _P, _P, C.POINTER(PTARecord)],
     "ptamd_get_num_atoms": [_SYS, C.POINTER(C.c_int64)],
     "ptamd_get_state": [_SYS, _P, _P, _P, _P, _P, _P],
     "ptamd_set_state": [_SYS, _P, _P, _P, _P, _P, _P],
@@ -133,6 +173,21 @@ def sc_params(eps=0.0033147, a=4.05, n=7.0, m=6.0, c=16.399, rc=8.1, shift=2) ->
 
 def md_params(dt_fs=1.0, tau_fs=100.0, thermostat=1, precision=0, skin=1.0, lanes_per_atom=0) -> MDParams:
     return MDParams(dt_fs, tau_fs, thermostat, precision, skin, lanes_per_atom)
+
+
+def conv_params(lag=1000, n_max=50000, tol=(0.05, 0.05, 0.0, 0.05), floor=(0.0, 0.0, 0.0, 0.0)) -> ConvParams:
+    """Convergence test of the running averages; tolerances and floors in the
+    order K, U, sigma_zz, T_z (defaults: Table 1's 5% on K, U and the reaction
+    stress, N_max = 50000)."""
+    return ConvParams(lag, n_max, (C.c_double * 4)(*tol), (C.c_double * 4)(*floor))
+
+
+def pta_params(d_eps_h: float, delta_over_h: float = 0.2, conv: Optional[ConvParams] = None,
+               tol_v=(0.01, 0.05, 0.01, 0.01), tol_j=(0.08, 0.01, 0.05, 0.05)) -> PTAParams:
+    """Slow-time driver parameters; tolerances in the order K, U, sigma_zz, T_z
+    (defaults: Table 1, the reaction-stress values also for sigma_zz)."""
+    return PTAParams(d_eps_h, delta_over_h, conv if conv is not None else conv_params(),
+                     (C.c_double * 4)(*tol_v), (C.c_double * 4)(*tol_j))
 
 
 def lattice_desc(n_cells: int, T0: float = 300.0, seed: int = 1, lattice_a: float = 4.05,
@@ -193,6 +248,42 @@ def run_fast_md(sys: int, n_steps: int) -> list:
     out = (Averages * nr)()
     _check(_lib.ptamd_run_fast_md(sys, n_steps, out))
     return [o.as_dict() for o in out]
+
+
+def run_until_converged(sys: int, conv: ConvParams) -> tuple:
+    """Returns (averages per replica, N_s per replica (0: not converged))."""
+    nr = get_info(sys)["n_replicas"]
+    out = (Averages * nr)()
+    n_conv = np.zeros(nr, np.int64)
+    _check(_lib.ptamd_run_until_converged(sys, C.byref(conv), out, _ptr(n_conv)))
+    return [o.as_dict() for o in out], n_conv
+
+
+def pta_start(sys: int, prm: PTAParams):
+    """Returns (ctypes array of PTAState, list of record dicts), one per replica."""
+    nr = get_info(sys)["n_replicas"]
+    st = (PTAState * nr)()
+    rec = (PTARecord * nr)()
+    _check(_lib.ptamd_pta_start(sys, C.byref(prm), st, rec))
+    return st, [r.as_dict() for r in rec]
+
+
+def pta_jump(sys: int, prm: PTAParams, states) -> list:
+    """Advances ``states`` (from pta_start) in place by one slow jump."""
+    nr = get_info(sys)["n_replicas"]
+    rec = (PTARecord * nr)()
+    _check(_lib.ptamd_pta_jump(sys, C.byref(prm), states, rec))
+    return [r.as_dict() for r in rec]
+
+
+def pta_update(prm: PTAParams, state: PTAState, R, strains, n_steps) -> dict:
+    """Host-only arithmetic of one slow step (no device needed); advances ``state``."""
+    Ra = np.ascontiguousarray(R, np.float64).reshape(3, 4)
+    sa = np.ascontiguousarray(strains, np.float64)
+    na = np.ascontiguousarray(n_steps, np.int64)
+    rec = PTARecord()
+    _check(_lib.ptamd_pta_update(C.byref(prm), C.byref(state), _ptr(Ra), _ptr(sa), _ptr(na), C.byref(rec)))
+    return rec.as_dict()
 
 
 def get_num_atoms(sys: int) -> int:
@@ -343,6 +434,15 @@ class System:
 
     def run_fast_md(self, n_steps: int):
         return run_fast_md(self.h, n_steps)
+
+    def run_until_converged(self, conv: Optional[ConvParams] = None):
+        return run_until_converged(self.h, conv if conv is not None else conv_params())
+
+    def pta_start(self, prm: PTAParams):
+        return pta_start(self.h, prm)
+
+    def pta_jump(self, prm: PTAParams, states):
+        return pta_jump(self.h, prm, states)
 
     def get_state(self):
         return get_state(self.h)

@@ -168,65 +168,118 @@ __global__ void k_fill_u64(unsigned long long *p, int64_t n, unsigned long long 
 // ---------------------------------------------------------------------------
 // sampling of one completed step (thread 0 of the first block of a replica)
 // ---------------------------------------------------------------------------
-__device__ void record_sample(const Params &p, const Buffers &b, int r, int64_t s, const double *q, double lam) {
-  const RepInfo &rp = b.rep[r];
-  RepAcc &A = b.acc[r];
+// State functions of one sample (after the thermostat's rescaling by lambda):
+// m[0] = K, m[1] = U, m[2] = sigma_zz, m[3] = T_z, m[4] = T.  Every block of
+// a kick-drift launch evaluates them with this one function, so all blocks of
+// a replica agree bit for bit on what the replica's first block records.
+__device__ void sample_values(const Params &p, const RepInfo &rp, const double *q, double lam, double *m) {
   const double l2 = lam * lam;
   const double mv2 = q[Q_MV2], mvz2 = q[Q_MVZ2];
-  const double K = 0.5 * l2 * mv2;
-  const double T = (rp.dof > 0.0) ? l2 * mv2 / (rp.dof * p.kb) : 0.0;
-  const double U = q[Q_EPAIR] + q[Q_EMB];
   const double V = rp.volume0 * (1.0 + rp.strain);
-  const double szz = -(l2 * mvz2 + q[Q_WZZ]) / V * p.gpa;
-  const double tz = (rp.area0 > 0.0) ? q[Q_RZ] / rp.area0 * p.gpa : 0.0;
-  A.sum[0] += K;
-  A.sum[1] += U;
-  A.sum[2] += szz;
-  A.sum[3] += T;
-  A.sum[4] += lam;
-  A.sum[5] += tz;
-  const int64_t bs = b.ctl->se_block;
-  if (bs > 0) {
-    const int64_t bi = (s - 1) / bs;
+  m[0] = 0.5 * l2 * mv2;
+  m[1] = q[Q_EPAIR] + q[Q_EMB];
+  m[2] = -(l2 * mvz2 + q[Q_WZZ]) / V * p.gpa;
+  m[3] = (rp.area0 > 0.0) ? q[Q_RZ] / rp.area0 * p.gpa : 0.0;
+  m[4] = (rp.dof > 0.0) ? l2 * mv2 / (rp.dof * p.kb) : 0.0;
+}
+
+// Column of the running sums that holds state function c (K, U, sigma_zz, T_z).
+__device__ __forceinline__ int sum_col(int c) { return c == 3 ? 5 : c; }
+
+// Sample s (1-based) of replica r: running sums, batch sums, series row.
+__device__ void record_sample(const Params &p, const Buffers &b, int r, int64_t s, const double *q, double lam) {
+  RepAcc &A = b.acc[r];
+  double m[5];
+  sample_values(p, b.rep[r], q, lam, m);
+  const double *S0 = A.sum[(s - 1) & 1];
+  double *S1 = A.sum[s & 1];
+  S1[0] = S0[0] + m[0];
+  S1[1] = S0[1] + m[1];
+  S1[2] = S0[2] + m[2];
+  S1[3] = S0[3] + m[4];
+  S1[4] = S0[4] + lam;
+  S1[5] = S0[5] + m[3];
+  const int64_t bs0 = b.ctl->se_block;
+  if (bs0 > 0) {
+    int64_t bs = A.se_bs > 0 ? A.se_bs : bs0;
+    int64_t bi = A.nsamp / bs;
+    if (b.ctl->conv_lag > 0 && bi >= kSEBlocks) {
+      // open-ended run: merge neighbouring batches, doubling their length
+      for (int j = 0; j < kSEBlocks / 2; ++j)
+        for (int c = 0; c < 3; ++c) A.blk[j][c] = A.blk[2 * j][c] + A.blk[2 * j + 1][c];
+      for (int j = kSEBlocks / 2; j < kSEBlocks; ++j)
+        for (int c = 0; c < 3; ++c) A.blk[j][c] = 0.0;
+      bs *= 2;
+      bi = A.nsamp / bs;
+    }
+    A.se_bs = bs;
     if (bi < kSEBlocks) {
-      A.blk[bi][0] += K;
-      A.blk[bi][1] += U;
-      A.blk[bi][2] += szz;
+      A.blk[bi][0] += m[0];
+      A.blk[bi][1] += m[1];
+      A.blk[bi][2] += m[2];
     }
   }
   if (s - 1 < b.series_cap) {
     double *row = b.series + ((size_t)r * b.series_cap + (s - 1)) * kSeriesCols;
-    row[0] = K; row[1] = U; row[2] = szz; row[3] = T; row[4] = lam; row[5] = tz;
+    row[0] = m[0]; row[1] = m[1]; row[2] = m[2]; row[3] = m[4]; row[4] = lam; row[5] = m[3];
   }
   A.nsamp += 1;
   A.lam_last = lam;
-  if (!isfinite(K) || !isfinite(U) || !isfinite(szz)) set_err(b, E_NONFINITE);
+  if (!isfinite(m[0]) || !isfinite(m[1]) || !isfinite(m[2])) set_err(b, E_NONFINITE);
 }
 
+// Convergence of the running averages at checkpoint i (a multiple of the
+// lag k, i >= 2k): for every tested state function, the relative change of
+// the running average over the last k samples, |R(i) - R(i-k)| / |R(i)|, is
+// below its tolerance (the denominator bounded below by the function's
+// floor).  m holds sample i, not yet added to the sums.
+__device__ bool averages_converged(const Buffers &b, int r, int64_t i, int64_t lag, const double *m) {
+  const RepAcc &A = b.acc[r];
+  const Control &c = *b.ctl;
+  const double *S = A.sum[(i - 1) & 1];
+  const double *C = A.csum[((i / lag) - 1) & 1];
+  for (int f = 0; f < 4; ++f) {
+    const double tol = c.conv_tol[f];
+    if (!(tol > 0.0)) continue;
+    const double ri = (S[sum_col(f)] + m[f]) / (double)i;
+    const double rk = C[f] / (double)(i - lag);
+    const double den = fmax(fabs(ri), c.conv_floor[f]);
+    const double e = fabs(ri - rk) / den;
+    if (!(e < tol)) return false;
+  }
+  return true;
+}
+
+
+// Averages over the samples so far; batch standard errors from the complete
+// batches (20 of n / 20 for a fixed-length burst, 10 to 20 for an open-ended one).
 __device__ void write_averages(const Buffers &b, int r) {
   RepAcc &A = b.acc[r];
   const double n = (double)A.nsamp;
-  A.out[0] = A.sum[0] / n;
-  A.out[1] = A.sum[1] / n;
-  A.out[2] = A.sum[2] / n;
-  A.out[3] = A.sum[5] / n;
-  const int64_t bs = b.ctl->se_block;
+  const double *S = A.sum[A.nsamp & 1];
+  A.out[0] = S[0] / n;
+  A.out[1] = S[1] / n;
+  A.out[2] = S[2] / n;
+  A.out[3] = S[5] / n;
+  const int64_t bs = A.se_bs;
+  int64_t nb = 0;
+  if (bs > 0) nb = (b.ctl->conv_lag > 0) ? min((int64_t)kSEBlocks, A.nsamp / bs) : (int64_t)kSEBlocks;
   for (int q = 0; q < 3; ++q) {
     double se = NAN;
-    if (bs > 0) {
+    if (nb >= 2) {
       double mu = 0.0, m[kSEBlocks];
-      for (int k = 0; k < kSEBlocks; ++k) {
+      for (int k = 0; k < nb; ++k) {
         m[k] = A.blk[k][q] / (double)bs;
         mu += m[k];
       }
-      mu /= (double)kSEBlocks;
+      mu /= (double)nb;
       double v = 0.0;
-      for (int k = 0; k < kSEBlocks; ++k) v += (m[k] - mu) * (m[k] - mu);
-      se = sqrt(v / (double)(kSEBlocks * (kSEBlocks - 1)));
+      for (int k = 0; k < nb; ++k) v += (m[k] - mu) * (m[k] - mu);
+      se = sqrt(v / (double)(nb * (nb - 1)));
     }
     A.out[4 + q] = se;
   }
-  A.out[7] = A.sum[3] / n;
+  A.out[7] = S[3] / n;
   A.out[8] = b.rep[r].strain;
   A.out[9] = n;
 }
@@ -252,7 +305,11 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(Params p, Buffers b, int3
     xr = b.xr[i]; yr = b.yr[i]; zr = b.zr[i];
   }
   const int64_t step = b.ctl->base + k;  // mode 0: step being computed; mode 1: n_steps + 1
+  // a replica whose running averages converged stays frozen for the rest of
+  // the burst (the whole block leaves together)
+  if (p.conv && b.acc[r].conv_step != 0) return;
   __shared__ double s_lam;
+  __shared__ int s_stop;
   if (threadIdx.x < 64) {
     // both parities' rows are loaded before the step index arrives
     const unsigned long long *row0 = slot_row(b, p.n_rep, 0, r, threadIdx.x);
@@ -274,6 +331,7 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(Params p, Buffers b, int3
     }
     if (threadIdx.x == 0) {
       double lam = 1.0;
+      int stop = 0;
       if (step > 1) {
         double qd[6];
         for (int t = 0; t < 6; ++t) qd[t] = (double)q[t] / kFix;
@@ -287,12 +345,29 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(Params p, Buffers b, int3
             lam = sqrt(l2);
           }
         }
+        const int64_t smp = step - 1;  // the sample this launch completes
+        const int64_t lag = p.conv ? b.ctl->conv_lag : 0;
+        const bool check = lag > 0 && smp % lag == 0;
+        if (check && smp >= 2 * lag) {
+          // every block of the replica takes the same decision from the same data
+          double m[5];
+          sample_values(p, rp, qd, lam, m);
+          stop = averages_converged(b, r, smp, lag, m) ? 1 : 0;
+        }
         if (tile == rp.abeg / kTile) {
-          record_sample(p, b, r, step - 1, qd, lam);
-          if (mode == 1) write_averages(b, r);
+          record_sample(p, b, r, smp, qd, lam);
+          RepAcc &A = b.acc[r];
+          if (check) {
+            const double *S = A.sum[smp & 1];
+            double *C = A.csum[(smp / lag) & 1];
+            for (int f = 0; f < 4; ++f) C[f] = S[sum_col(f)];
+          }
+          if (stop) A.conv_step = smp;
+          if (stop || mode == 1) write_averages(b, r);
         }
       }
       s_lam = lam;
+      s_stop = stop;
     }
   }
   __syncthreads();
@@ -301,7 +376,7 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(Params p, Buffers b, int3
   vx *= lam;
   vy *= lam;
   vz *= lam;
-  if (mode == 0) {
+  if (mode == 0 && !s_stop) {
     vx += p.hdt_m * fx;
     vy += p.hdt_m * fy;
     vz += p.hdt_m * fz;
@@ -492,6 +567,7 @@ __global__ __launch_bounds__(kBlock) void k_density(Params p, Buffers b, int32_t
     unsigned long long *zp = b.slots + (size_t)(par ^ 1) * nz;
     for (size_t t = (size_t)gt; t < nz; t += (size_t)gridDim.x * kBlock) zp[t] = 0ull;
   }
+  if (p.conv && b.acc[r].conv_step != 0) return;  // converged replica: frozen
   const uint8_t g = b.group[i];
   const bool real = g != kPad;
   const V4 *p4 = reinterpret_cast<const V4 *>(b.pos4);
@@ -557,6 +633,7 @@ __global__ __launch_bounds__(kBlock) void k_force(Params p, Buffers b, int32_t k
   const int r = b.blk_rep[tile];
   const int64_t step = b.ctl->base + k;
   const int par = (int)(step & 1);
+  if (p.conv && b.acc[r].conv_step != 0) return;  // converged replica: frozen
   const uint8_t g = b.group[i];
   const bool real = g != kPad;
   const V4 *p4 = reinterpret_cast<const V4 *>(b.pos4);

@@ -44,8 +44,12 @@ struct Control {
   int32_t spare;
   int32_t err;       // error bits
   int64_t n_steps;   // steps of the current burst
-  int64_t se_block;  // samples per standard-error block (n_steps / 20)
+  int64_t se_block;  // samples per standard-error block (n_steps / 20; lag / 10 when testing convergence)
   int64_t ncells;    // cells of all replicas (binning grid of the last sort)
+  // convergence test of the running averages (0: fixed-length burst)
+  int64_t conv_lag;       // k: checks at samples 2k, 3k, ..., each against the average k samples earlier
+  double conv_tol[4];     // tolerance per state function (K, U, sigma_zz, T_z); <= 0: not tested
+  double conv_floor[4];   // lower bound of the error's denominator (0: the plain relative error)
 };
 
 constexpr int kStat = 16;  // u64 entries per statistics row
@@ -67,10 +71,18 @@ struct RepInfo {
 };
 
 // Per-replica burst accumulators (device memory).
+// The running sums are kept twice, by the parity of the last sample they
+// hold: the kick-drift launch that records sample s reads sum[(s-1)&1] and
+// writes sum[s&1], so every block of that launch can read the sums through
+// s-1 while the replica's first block adds sample s.  The checkpoint sums of
+// the convergence test alternate the same way.
 struct RepAcc {
-  double sum[kSeriesCols];
-  double blk[kSEBlocks][3];
+  double sum[2][kSeriesCols];  // K, U, sigma_zz, T, lambda, T_z
+  double blk[kSEBlocks][3];    // batch sums of K, U, sigma_zz
+  double csum[2][4];           // sums of K, U, sigma_zz, T_z at the last two checkpoints
   int64_t nsamp;
+  int64_t se_bs;               // samples per batch (doubles when 20 batches are full, convergence mode)
+  int64_t conv_step;           // N_s once the averages converged (0 while running)
   double lam_last;
   double out[12];  // ke, pe, szz, tz, ke_se, pe_se, szz_se, temp, strain, n, spare...
 };
@@ -100,7 +112,7 @@ struct Params {
   int32_t cap_slots;   // list slots per lane (a multiple of kGroup)
   int32_t lpa;
   int32_t ktime;       // nonzero: the force kernel stamps per-block start/end times into Buffers::ktime
-  int32_t pad2;
+  int32_t conv;        // nonzero: replicas whose averages converged are skipped (Control::conv_lag > 0)
 };
 
 // Device buffers (pointers), passed by value.

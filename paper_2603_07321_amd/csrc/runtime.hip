@@ -33,6 +33,9 @@ struct Failure {
 
 static thread_local std::string g_last_error;
 
+// message of the last failed call on this thread (also set by the slow-time driver)
+void set_last_error(const std::string &msg) { g_last_error = msg; }
+
 template <class T> static T *dalloc(size_t n) {
   if (n == 0) n = 1;
   void *p = nullptr;
@@ -48,7 +51,6 @@ static void dfree(void *p) {
 constexpr int kMaxDims = 128;       // binning grid cells per axis (atoms beyond are clamped into edge cells)
 constexpr int kMaxChunk = 256;     // steps per captured graph
 constexpr int kMinChunk = 4;
-constexpr int kStartChunk = 64;
 
 struct RepHost {
   int64_t abeg = 0, aend = 0, nreal = 0, nmob = 0;
@@ -524,7 +526,7 @@ static void sort_system(ptamd_system *s) {
 // ---------------------------------------------------------------------------
 // Graph of K whole steps; with_build puts a Verlet-list build in front.
 static GraphEntry &get_graph(ptamd_system *s, int K, bool with_build) {
-  const int key = 2 * K + (with_build ? 1 : 0);
+  const int key = 4 * K + (s->P.conv ? 2 : 0) + (with_build ? 1 : 0);
   auto it = s->graphs.find(key);
   if (it != s->graphs.end()) return it->second;
   GraphEntry g;
@@ -624,13 +626,49 @@ static ChunkStats chunk_stats(ptamd_system *s) {
   return cs;
 }
 
-static void run_burst(ptamd_system *s, int64_t n_steps, ptamd_averages *out) {
+// Burst of n_steps steps, or (conv != nullptr) of at most conv->n_max steps
+// that each replica ends at the first checkpoint where its running averages
+// pass the convergence test (n_conv[r] = that step, else 0).
+static void run_burst(ptamd_system *s, int64_t n_steps, ptamd_averages *out, const ptamd_conv_params *conv = nullptr,
+                      int64_t *n_conv = nullptr) {
+  int64_t lag = 0;
+  if (conv) {
+    lag = conv->lag;
+    n_steps = conv->n_max;
+    if (lag < 1 || n_steps < 2 * lag) fail(PTAMD_EINVAL, "need lag >= 1 and n_max >= 2 lag");
+    bool any = false;
+    for (int f = 0; f < 4; ++f) {
+      if (!std::isfinite(conv->tol[f]) || !std::isfinite(conv->floor[f]) || conv->floor[f] < 0.0)
+        fail(PTAMD_EINVAL, "tolerances and floors must be finite, floors >= 0");
+      any = any || conv->tol[f] > 0.0;
+    }
+    if (!any) fail(PTAMD_EINVAL, "no state function is tested (all tol <= 0)");
+  }
   if (n_steps < 1) fail(PTAMD_EINVAL, "n_steps must be >= 1");
   ensure_series(s, n_steps);
   struct {
     int64_t n, se;
-  } hdr{n_steps, n_steps >= kSEBlocks ? n_steps / kSEBlocks : 0};
+  } hdr{n_steps, conv ? std::max<int64_t>(1, lag / 10) : (n_steps >= kSEBlocks ? n_steps / kSEBlocks : 0)};
   h2d(s, &s->B.ctl->n_steps, &hdr, sizeof(hdr));
+  struct {
+    int64_t lag;
+    double tol[4], floor[4];
+  } ch{};
+  ch.lag = lag;
+  for (int f = 0; f < 4 && conv; ++f) {
+    ch.tol[f] = conv->tol[f];
+    ch.floor[f] = conv->floor[f];
+  }
+  h2d(s, &s->B.ctl->conv_lag, &ch, sizeof(ch));
+  // the convergence flag is part of the captured kernel arguments (graphs are
+  // keyed by it); it is cleared again however the burst ends
+  struct ConvScope {
+    Params &P;
+    ConvScope(Params &p, bool on) : P(p) { P.conv = on ? 1 : 0; }
+    ~ConvScope() { P.conv = 0; }
+  } conv_scope(s->P, conv != nullptr);
+  const bool timing = s->timing && !conv;
+  std::vector<RepAcc> acc(s->n_rep);
   initial_forces(s);
   ChunkStats st = chunk_stats(s);
   int64_t step = 1;
@@ -653,10 +691,16 @@ static void run_burst(ptamd_system *s, int64_t n_steps, ptamd_averages *out) {
     int K = (int)std::min<double>({(skin_room - st.ldisp) / vb, (0.8 * s->margin - st.drift) / vb, (double)chunk});
     K = std::max(K, kMinChunk);
     K = (int)std::min<int64_t>(K, n_steps - step + 1);
+    if (conv) {
+      // end the chunk with the launch that decides the next checkpoint c
+      // (the kick-drift of step c + 1), so a finished burst stops promptly
+      const int64_t c = std::max<int64_t>(2 * lag, (step - 1 + lag - 1) / lag * lag);
+      if (c + 1 >= step) K = (int)std::min<int64_t>(K, c + 1 - step + 1);
+    }
     snapshot(s, false);
     launch_set_base(s->B, step, s->stream);
     int done = 0;
-    if (s->timing) {
+    if (timing) {
       // the chunk's first step is launched directly, its force kernel bracketed
       // by events on the system's stream; the rest of the chunk is a graph
       if (build) launch_build(s->P, s->B, s->precision, s->lpa, s->stream);
@@ -671,7 +715,7 @@ static void run_burst(ptamd_system *s, int64_t n_steps, ptamd_averages *out) {
       if (K > 1) launch_set_base(s->B, step + 1, s->stream);
     }
     check_launch();
-    if (K > done) HIPCHK(hipGraphLaunch(get_graph(s, K - done, build && !s->timing).exec, s->stream));
+    if (K > done) HIPCHK(hipGraphLaunch(get_graph(s, K - done, build && !timing).exec, s->stream));
     st = chunk_stats(s);
     const int err = s->h_ctl->err;
     if (err & (E_DRIFT | E_OVERFLOW | E_SKIN)) {
@@ -692,7 +736,7 @@ static void run_burst(ptamd_system *s, int64_t n_steps, ptamd_averages *out) {
       s->list_builds++;
       s->need_build = false;
     }
-    if (s->timing) {
+    if (timing) {
       float ms = 0.f;
       HIPCHK(hipEventElapsedTime(&ms, s->ev0, s->ev1));
       s->t_ev_ms += ms;
@@ -710,12 +754,18 @@ static void run_burst(ptamd_system *s, int64_t n_steps, ptamd_averages *out) {
     step += K;
     s->steps_total += K;
     chunk = std::min(kMaxChunk, chunk * 2);
+    if (conv) {
+      d2h(s, acc.data(), s->B.acc, sizeof(RepAcc) * s->n_rep);
+      bool all = true;
+      for (int r = 0; r < s->n_rep && all; ++r) all = acc[r].conv_step != 0;
+      if (all) break;
+    }
   }
-  // finalize: lambda of the last step, its sample, the averages
+  // finalize: lambda of the last step, its sample, the averages (replicas
+  // that converged skip this launch: theirs are final)
   launch_set_base(s->B, n_steps + 1, s->stream);
   launch_kick_drift(s->P, s->B, s->precision, 0, 1, s->stream);
   check_launch();
-  std::vector<RepAcc> acc(s->n_rep);
   HIPCHK(hipMemcpyAsync(acc.data(), s->B.acc, sizeof(RepAcc) * s->n_rep, hipMemcpyDeviceToHost, s->stream));
   HIPCHK(hipMemcpyAsync(s->h_ctl, s->B.ctl, sizeof(Control), hipMemcpyDeviceToHost, s->stream));
   sync(s);
@@ -732,6 +782,7 @@ static void run_burst(ptamd_system *s, int64_t n_steps, ptamd_averages *out) {
     out[r].temp = o[7];
     out[r].strain = o[8];
     out[r].n_samples = (int64_t)o[9];
+    if (n_conv) n_conv[r] = acc[r].conv_step;
   }
 }
 
@@ -1156,6 +1207,15 @@ ptamd_status ptamd_run_fast_md(ptamd_system *sys, int64_t n_steps, ptamd_average
     use_device(sys);
     if (!out) fail(PTAMD_EINVAL, "out is NULL");
     run_burst(sys, n_steps, out);
+  });
+}
+
+ptamd_status ptamd_run_until_converged(ptamd_system *sys, const ptamd_conv_params *conv, ptamd_averages *out,
+                                       int64_t *n_conv) {
+  return guard([&] {
+    use_device(sys);
+    if (!conv || !out || !n_conv) fail(PTAMD_EINVAL, "conv, out and n_conv must not be NULL");
+    run_burst(sys, 0, out, conv, n_conv);
   });
 }
 
