@@ -189,6 +189,36 @@ typedef struct {
 ptamd_status ptamd_run_until_converged(ptamd_system *sys, const ptamd_conv_params *conv, ptamd_averages *out,
                                        int64_t *n_conv);
 
+/* ---- further observables of the paper ---- */
+/* Per-atom mean positions of Eq. (mean_pos): with enable != 0 every later
+ * burst also sums each atom's position over its samples r = 1..N_t (FP64,
+ * 24 more bytes of device memory per atom; the sums follow the atoms through
+ * re-sorts and roll-backs).  enable = 0 frees them. */
+ptamd_status ptamd_set_mean_positions(ptamd_system *sys, int32_t enable);
+/* Mean positions over the samples of the last burst (per replica its own
+ * N_t: n_samples of its averages), original order, all replicas
+ * concatenated.  PTAMD_ESTATE if switched off, or if no burst has run since
+ * they were switched on or since another call evaluated forces. */
+ptamd_status ptamd_get_mean_positions(ptamd_system *sys, double *x, double *y, double *z);
+
+/* Thermal relaxation before loading (Sec. 2.4.2): the atoms of the top
+ * region (group 2) move freely along z, each on its own, held along x and
+ * y, while bursts of burst_steps run; the thermostat then also acts on
+ * them, with one degree of freedom each.  It ends when the burst-averaged
+ * reaction stress |T_z| of every replica is below tol_gpa, or after
+ * max_bursts bursts; the top region is then held again where it stands
+ * (v = 0).  The paper does not give a tolerance. */
+typedef struct {
+    int64_t burst_steps;   /* >= 1 */
+    int64_t max_bursts;    /* >= 1 */
+    double tol_gpa;        /* >= 0 */
+} ptamd_relax_params;
+/* out: the averages of the last burst, per replica; n_bursts: bursts run;
+ * relaxed[r]: 1 if replica r met the tolerance in the last burst.  Every
+ * replica needs a top region. */
+ptamd_status ptamd_relax(ptamd_system *sys, const ptamd_relax_params *prm, ptamd_averages *out, int64_t *n_bursts,
+                         int32_t *relaxed);
+
 /* ---- the PTA slow-time driver (Sec. 2.2 Steps 1-4, Sec. 2.4.2) ----
  * One slow step t -> t+h takes three converged runs (ptamd_run_until_converged)
  * at the strains of slow times t+h-Delta, t+h-Delta/2 and t+h, each started

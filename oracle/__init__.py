@@ -45,7 +45,8 @@ class SC(C.Structure):
 
 
 class MD(C.Structure):
-    _fields_ = [("dt", C.c_double), ("tau", C.c_double), ("T0", C.c_double), ("thermostat", C.c_int32)]
+    _fields_ = [("dt", C.c_double), ("tau", C.c_double), ("T0", C.c_double), ("thermostat", C.c_int32),
+                ("top_free_z", C.c_int32)]
 
 
 class _State(C.Structure):
@@ -101,7 +102,7 @@ def lib():
     L.orc_cell_assign.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, C.c_double, _i32p, _i32p]
     L.orc_run_burst.restype = C.c_int32
     L.orc_run_burst.argtypes = [C.POINTER(_State), C.POINTER(SC), C.POINTER(MD), C.c_int64,
-                                C.POINTER(Averages), C.c_void_p]
+                                C.POINTER(Averages), C.c_void_p, C.c_void_p]
     L.orc_apply_strain.argtypes = [C.POINTER(_State), C.c_double]
     L.orc_observables.argtypes = [C.POINTER(_State), C.POINTER(SC)] + [C.POINTER(C.c_double)] * 4
     _lib = L
@@ -112,8 +113,8 @@ def sc_params(eps=0.0033147, a=4.05, n=7.0, m=6.0, c=16.399, rc=8.1, shift=2) ->
     return SC(eps, a, n, m, c, rc, shift)
 
 
-def md_params(dt=1.0, tau=100.0, T0=300.0, thermostat=1) -> MD:
-    return MD(dt, tau, T0, thermostat)
+def md_params(dt=1.0, tau=100.0, T0=300.0, thermostat=1, top_free_z=0) -> MD:
+    return MD(dt, tau, T0, thermostat, top_free_z)
 
 
 def constants():
@@ -263,16 +264,40 @@ def create_cube(nc: int, T0: float, seed: int, a: float = 4.05, fix_slabs: bool 
     return State(x, y, z, vx, vy, vz, g, volume0=float(nc) ** 3 * a ** 3, area0=(nc * a) ** 2)
 
 
-def run_burst(st: State, p: SC, md: MD, n_steps: int, series: bool = False):
-    """Advance ``st`` in place by n_steps; returns (averages dict, series array or None)."""
+def run_burst(st: State, p: SC, md: MD, n_steps: int, series: bool = False, mean_positions: bool = False):
+    """Advance ``st`` in place by n_steps; returns (averages dict, series array
+    or None), plus the per-atom mean positions (3, n) of Eq. (mean_pos) when
+    ``mean_positions``."""
     cs = st._cstate()
     avg = Averages()
     ser = np.zeros((n_steps, len(SER_COLS)), D) if series else None
+    psum = np.zeros(3 * st.n, D) if mean_positions else None
     rc = lib().orc_run_burst(C.byref(cs), C.byref(p), C.byref(md), n_steps, C.byref(avg),
-                             ser.ctypes.data if ser is not None else None)
+                             ser.ctypes.data if ser is not None else None,
+                             psum.ctypes.data if psum is not None else None)
     if rc != 0:
         raise RuntimeError(f"oracle burst failed with status {rc}")
+    if mean_positions:
+        return avg.as_dict(), ser, psum.reshape(3, st.n) / n_steps
     return avg.as_dict(), ser
+
+
+def relax(st: State, p: SC, md: MD, burst_steps: int, max_bursts: int, tol_gpa: float):
+    """Thermal relaxation of Sec. 2.4.2: bursts with the top region free along
+    z until |burst-averaged reaction stress| < tol_gpa (at most max_bursts),
+    then the region is held again (v = 0).  Returns (last averages, bursts,
+    relaxed)."""
+    free = MD(md.dt, md.tau, md.T0, md.thermostat, 1)
+    k, ok, avg = 0, False, None
+    while not ok and k < max_bursts:
+        avg, _ = run_burst(st, p, free, burst_steps)
+        k += 1
+        ok = abs(avg["tz"]) < tol_gpa
+    top = st.group == 2
+    st.vx[top] = 0.0
+    st.vy[top] = 0.0
+    st.vz[top] = 0.0
+    return avg, k, ok
 
 
 def apply_strain(st: State, d_eps: float) -> None:

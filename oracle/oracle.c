@@ -382,17 +382,26 @@ void orc_apply_strain(orc_state *s, double d_eps) {
     s->strain = e_new;
 }
 
-static void kinetic_sums(const orc_state *s, int64_t *nmob, double *mv2, double *mvz2) {
+/* Which atoms the integrator moves: mobile atoms (group 0) along x, y and z;
+ * during thermal relaxation (Sec. 2.4.2) the top-region atoms (group 2) move
+ * along the load axis z only; every other fixed atom keeps v = 0, F = 0. */
+static int moves_xyz(uint8_t g) { return g == 0; }
+static int moves_z(uint8_t g, const orc_md *md) { return g == 0 || (g == 2 && md->top_free_z); }
+
+/* m v^2 and m v_z^2 summed over the atoms that move, and the degrees of
+ * freedom of the thermostat: 3 N_mob - 3, plus one per top atom free in z. */
+static void kinetic_sums(const orc_state *s, const orc_md *md, double *dof, double *mv2, double *mvz2) {
     const double m = orc_mass_al();
     double a = 0.0, b = 0.0;
-    int64_t c = 0;
+    int64_t c = 0, t = 0;
     for (int64_t i = 0; i < s->n; ++i) {
-        if (s->group[i] != 0) continue;
+        if (!moves_z(s->group[i], md)) continue;
         a += m * (s->vx[i] * s->vx[i] + s->vy[i] * s->vy[i] + s->vz[i] * s->vz[i]);
         b += m * s->vz[i] * s->vz[i];
-        ++c;
+        if (moves_xyz(s->group[i])) ++c; else ++t;
     }
-    *nmob = c; *mv2 = a; *mvz2 = b;
+    *dof = 3.0 * (double)c - 3.0 + (double)t;
+    *mv2 = a; *mvz2 = b;
 }
 
 /* sigma_zz = -(1/V) (sum_mob m v_z^2 + W_zz), tension positive. */
@@ -405,9 +414,9 @@ void orc_observables(const orc_state *s, const orc_sc *p, double *K, double *U, 
     double *f = (double *)malloc(sizeof(double) * (size_t)(3 * n));
     double u, w, rz;
     orc_forces(n, s->x, s->y, s->z, s->group, p, f, f + n, f + 2 * n, NULL, &u, &w, &rz);
-    int64_t nm;
-    double mv2, mvz2;
-    kinetic_sums(s, &nm, &mv2, &mvz2);
+    const orc_md fixed_top = {1.0, 1.0, 0.0, 0, 0};
+    double dof, mv2, mvz2;
+    kinetic_sums(s, &fixed_top, &dof, &mv2, &mvz2);
     *K = 0.5 * mv2 * orc_mvv2e();
     *U = u;
     *szz = stress_zz(s, mvz2, w);
@@ -433,7 +442,7 @@ static void block_se(const double *col, int64_t stride, int64_t n, double *se) {
 }
 
 int32_t orc_run_burst(orc_state *s, const orc_sc *p, const orc_md *md, int64_t n_steps,
-                      orc_averages *avg, double *series) {
+                      orc_averages *avg, double *series, double *pos_sum) {
     const int64_t n = s->n;
     const double m = orc_mass_al(), kb = orc_kb(), c = orc_mvv2e();
     /* acceleration = F/m in A/fs^2 with F in eV/A: divide by m * c. */
@@ -447,39 +456,49 @@ int32_t orc_run_burst(orc_state *s, const orc_sc *p, const orc_md *md, int64_t n
     int32_t status = 0;
     double U, W, Rz;
 
-    /* forces at the burst start are recomputed from the positions */
+    /* forces at the burst start are recomputed from the positions; the
+     * components along which an atom is held are zeroed (F = 0 of the
+     * fixed regions) */
     orc_forces(n, s->x, s->y, s->z, s->group, p, fx, fy, fz, NULL, &U, &W, &Rz);
-    for (int64_t i = 0; i < n; ++i)
-        if (s->group[i] != 0) fx[i] = fy[i] = fz[i] = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (!moves_xyz(s->group[i])) fx[i] = fy[i] = 0.0;
+        if (!moves_z(s->group[i], md)) fz[i] = 0.0;
+    }
+    if (pos_sum)
+        for (int64_t i = 0; i < 3 * n; ++i) pos_sum[i] = 0.0;
 
     double sk = 0.0, su = 0.0, ss = 0.0, st = 0.0, stz = 0.0;
     for (int64_t r = 1; r <= n_steps; ++r) {
         /* Eq. (vv_algo_pos_pred_half) and Eq. (vv_algo_pos_pred); fixed atoms
          * have v = 0 and F = 0 and therefore do not move. */
         for (int64_t i = 0; i < n; ++i) {
-            if (s->group[i] != 0) continue;
-            s->vx[i] += hdt_m * fx[i];
-            s->vy[i] += hdt_m * fy[i];
-            s->vz[i] += hdt_m * fz[i];
-            s->x[i] += md->dt * s->vx[i];
-            s->y[i] += md->dt * s->vy[i];
-            s->z[i] += md->dt * s->vz[i];
+            if (moves_xyz(s->group[i])) {
+                s->vx[i] += hdt_m * fx[i];
+                s->vy[i] += hdt_m * fy[i];
+                s->vz[i] += hdt_m * fz[i];
+                s->x[i] += md->dt * s->vx[i];
+                s->y[i] += md->dt * s->vy[i];
+                s->z[i] += md->dt * s->vz[i];
+            } else if (moves_z(s->group[i], md)) {
+                s->vz[i] += hdt_m * fz[i];
+                s->z[i] += md->dt * s->vz[i];
+            }
         }
         /* new internal forces, energy, virial and reaction at r(sigma+dsigma) */
         orc_forces(n, s->x, s->y, s->z, s->group, p, fx, fy, fz, NULL, &U, &W, &Rz);
-        for (int64_t i = 0; i < n; ++i)
-            if (s->group[i] != 0) fx[i] = fy[i] = fz[i] = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            if (!moves_xyz(s->group[i])) fx[i] = fy[i] = 0.0;
+            if (!moves_z(s->group[i], md)) fz[i] = 0.0;
+        }
         /* Eq. (vv_algo_vel_pred) */
         for (int64_t i = 0; i < n; ++i) {
-            if (s->group[i] != 0) continue;
+            if (!moves_z(s->group[i], md)) continue;
             s->vx[i] += hdt_m * fx[i];
             s->vy[i] += hdt_m * fy[i];
             s->vz[i] += hdt_m * fz[i];
         }
-        int64_t nmob;
-        double mv2, mvz2;
-        kinetic_sums(s, &nmob, &mv2, &mvz2);
-        const double dof = 3.0 * (double)nmob - 3.0;
+        double dof, mv2, mvz2;
+        kinetic_sums(s, md, &dof, &mv2, &mvz2);
         double lam = 1.0;
         if (md->thermostat) {
             /* Berendsen: lambda^2 = 1 + (dt/tau)(T0/T - 1), applied to the
@@ -489,11 +508,18 @@ int32_t orc_run_burst(orc_state *s, const orc_sc *p, const orc_md *md, int64_t n
             if (!(T > 0.0) || !(l2 >= 0.0)) { status = -7; break; }
             lam = sqrt(l2);
             for (int64_t i = 0; i < n; ++i) {
-                if (s->group[i] != 0) continue;
+                if (!moves_z(s->group[i], md)) continue;
                 s->vx[i] *= lam; s->vy[i] *= lam; s->vz[i] *= lam;
             }
-            kinetic_sums(s, &nmob, &mv2, &mvz2);
+            kinetic_sums(s, md, &dof, &mv2, &mvz2);
         }
+        /* Eq. (mean_pos): positions of sample r enter the per-atom sums */
+        if (pos_sum)
+            for (int64_t i = 0; i < n; ++i) {
+                pos_sum[i] += s->x[i];
+                pos_sum[n + i] += s->y[i];
+                pos_sum[2 * n + i] += s->z[i];
+            }
         /* state functions of Eq. (state_variables) after the full step */
         const double K = 0.5 * mv2 * c;
         const double T = (dof > 0.0) ? mv2 * c / (dof * kb) : 0.0;

@@ -38,6 +38,8 @@ typedef struct {
     double tau;       /* fs, Berendsen coupling time */
     double T0;        /* K, thermostat target */
     int32_t thermostat; /* 0 = NVE, 1 = Berendsen */
+    int32_t top_free_z; /* 1: atoms of the top region (group 2) move along z only
+                           (thermal relaxation, Sec. 2.4.2); 0: they are fixed */
 } orc_md;
 
 /* Physical constants (CODATA 2018 / exact SI).  Written here independently
@@ -113,9 +115,11 @@ enum { ORC_SER_K = 0, ORC_SER_U, ORC_SER_SZZ, ORC_SER_T, ORC_SER_LAMBDA, ORC_SER
 
 /* Run n_steps velocity-Verlet steps from the state; forces are recomputed at
  * the start.  series (n_steps x ORC_SER_NCOL, row major) may be NULL.
- * Returns 0, or -7 if the thermostat meets T <= 0. */
+ * pos_sum (3n: x sums, then y, then z; may be NULL) receives the sum over the
+ * samples r = 1..n_steps of every atom's position, the numerator of
+ * Eq. (mean_pos).  Returns 0, or -7 if the thermostat meets T <= 0. */
 int32_t orc_run_burst(orc_state *s, const orc_sc *p, const orc_md *md, int64_t n_steps,
-                      orc_averages *avg, double *series);
+                      orc_averages *avg, double *series, double *pos_sum);
 /* eps_k = eps_{k-1} + d_eps; z <- z (1+eps_k)/(1+eps_{k-1}) for every atom. */
 void orc_apply_strain(orc_state *s, double d_eps);
 double orc_volume(const orc_state *s);

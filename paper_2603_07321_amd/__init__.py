@@ -66,6 +66,10 @@ class ConvParams(C.Structure):
     _fields_ = [("lag", C.c_int64), ("n_max", C.c_int64), ("tol", C.c_double * 4), ("floor", C.c_double * 4)]
 
 
+class RelaxParams(C.Structure):
+    _fields_ = [("burst_steps", C.c_int64), ("max_bursts", C.c_int64), ("tol_gpa", C.c_double)]
+
+
 class PTAParams(C.Structure):
     _fields_ = [("d_eps_h", C.c_double), ("delta_over_h", C.c_double), ("conv", ConvParams),
                 ("tol_v", C.c_double * 4), ("tol_j", C.c_double * 4)]
@@ -124,6 +128,9 @@ SIGNATURES = {
     "ptamd_apply_strain_increments": [_SYS, _P],
     "ptamd_run_fast_md": [_SYS, C.c_int64, C.POINTER(Averages)],
     "ptamd_run_until_converged": [_SYS, C.POINTER(ConvParams), C.POINTER(Averages), _P],
+    "ptamd_set_mean_positions": [_SYS, C.c_int32],
+    "ptamd_get_mean_positions": [_SYS, _P, _P, _P],
+    "ptamd_relax": [_SYS, C.POINTER(RelaxParams), C.POINTER(Averages), C.POINTER(C.c_int64), _P],
     "ptamd_pta_start": [_SYS, C.POINTER(PTAParams), C.POINTER(PTAState), C.POINTER(PTARecord)],
     "ptamd_pta_jump": [_SYS, C.POINTER(PTAParams), C.POINTER(PTAState), C.POINTER(PTARecord)],
     "ptamd_pta_update": [C.POINTER(PTAParams), C.POINTER(PTAState), _P, _P, _P, C.POINTER(PTARecord)],
@@ -257,6 +264,30 @@ def run_until_converged(sys: int, conv: ConvParams) -> tuple:
     n_conv = np.zeros(nr, np.int64)
     _check(_lib.ptamd_run_until_converged(sys, C.byref(conv), out, _ptr(n_conv)))
     return [o.as_dict() for o in out], n_conv
+
+
+def set_mean_positions(sys: int, enable: bool = True) -> None:
+    _check(_lib.ptamd_set_mean_positions(sys, int(bool(enable))))
+
+
+def get_mean_positions(sys: int) -> np.ndarray:
+    """(3, n) mean positions of Eq. (mean_pos) over the last burst's samples."""
+    n = get_num_atoms(sys)
+    out = np.zeros((3, n), np.float64)
+    _check(_lib.ptamd_get_mean_positions(sys, _ptr(out[0]), _ptr(out[1]), _ptr(out[2])))
+    return out
+
+
+def relax(sys: int, burst_steps: int, max_bursts: int, tol_gpa: float) -> tuple:
+    """Thermal relaxation with the top region free along z.  Returns (last
+    burst's averages per replica, bursts run, relaxed flags)."""
+    nr = get_info(sys)["n_replicas"]
+    out = (Averages * nr)()
+    nb = C.c_int64()
+    flags = np.zeros(nr, np.int32)
+    prm = RelaxParams(burst_steps, max_bursts, tol_gpa)
+    _check(_lib.ptamd_relax(sys, C.byref(prm), out, C.byref(nb), _ptr(flags)))
+    return [o.as_dict() for o in out], nb.value, flags.astype(bool)
 
 
 def pta_start(sys: int, prm: PTAParams):
@@ -437,6 +468,15 @@ class System:
 
     def run_until_converged(self, conv: Optional[ConvParams] = None):
         return run_until_converged(self.h, conv if conv is not None else conv_params())
+
+    def set_mean_positions(self, enable: bool = True):
+        set_mean_positions(self.h, enable)
+
+    def get_mean_positions(self):
+        return get_mean_positions(self.h)
+
+    def relax(self, burst_steps: int, max_bursts: int, tol_gpa: float):
+        return relax(self.h, burst_steps, max_bursts, tol_gpa)
 
     def pta_start(self, prm: PTAParams):
         return pta_start(self.h, prm)

@@ -144,13 +144,20 @@ __device__ __forceinline__ unsigned long long *slot_row(const Buffers &b, int n_
 
 __device__ __forceinline__ void set_err(const Buffers &b, int bits) { atomicOr(&b.ctl->err, bits); }
 
+// Atoms the integrator moves: mobile atoms (group 0) along x, y, z; during
+// thermal relaxation the top region (group 2) along z only.  Every other
+// atom is held (v = 0, F = 0).
+__device__ __forceinline__ bool moves_z(const Params &p, uint8_t g) { return g == 0 || (p.top_free && g == 2); }
+
 // ---------------------------------------------------------------------------
 // burst start: zero accumulators, slots and errors
 // ---------------------------------------------------------------------------
-__global__ void k_burst_begin(Buffers b, int n_rep) {
+__global__ void k_burst_begin(Buffers b, int n_rep, int64_t ntot) {
   const size_t nslot = (size_t)2 * n_rep * kSlots * kNQ;
   const size_t t0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (size_t t = t0; t < nslot; t += (size_t)gridDim.x * blockDim.x) b.slots[t] = 0ull;
+  if (b.msx)
+    for (size_t t = t0; t < (size_t)ntot; t += (size_t)gridDim.x * blockDim.x) b.msx[t] = b.msy[t] = b.msz[t] = 0.0;
   const size_t nacc = (size_t)n_rep * (sizeof(RepAcc) / sizeof(double));
   double *acc = reinterpret_cast<double *>(b.acc);
   for (size_t t = t0; t < nacc; t += (size_t)gridDim.x * blockDim.x) acc[t] = 0.0;
@@ -295,7 +302,9 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(Params p, Buffers b, int3
   const int64_t i = tile * kTile + threadIdx.x;
   // per-atom loads first: they stay in flight while wave 0 reduces lambda
   // every array covers the padded range, so these loads need not wait for the group
-  const bool mob = b.group[i] == 0;
+  const uint8_t grp = b.group[i];
+  const bool mob = moves_z(p, grp);
+  const bool zonly = grp != 0;  // a moving atom of the top region: along z only
   double vx = b.vx[i], vy = b.vy[i], vz = b.vz[i];
   double x = 0, y = 0, z = 0, fx = 0, fy = 0, fz = 0;
   float xr = 0.f, yr = 0.f, zr = 0.f;
@@ -371,12 +380,21 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(Params p, Buffers b, int3
     }
   }
   __syncthreads();
-  if (!mob) return;  // fixed or padding atom: v = 0, never moves
+  const bool step_on = mode == 0 && !s_stop;
+  if (!mob) {  // fixed or padding atom: v = 0, never moves
+    if (p.msum && step_on && grp != kPad) {
+      b.msx[i] += x;
+      b.msy[i] += y;
+      b.msz[i] += z;
+    }
+    return;
+  }
   const double lam = s_lam;
   vx *= lam;
   vy *= lam;
   vz *= lam;
-  if (mode == 0 && !s_stop) {
+  if (zonly) fx = fy = 0.0;  // held along x and y
+  if (step_on) {
     vx += p.hdt_m * fx;
     vy += p.hdt_m * fy;
     vz += p.hdt_m * fz;
@@ -398,6 +416,11 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(Params p, Buffers b, int3
     if (!(cx * cx + cy * cy + cz * cz <= p.esc2)) set_err(b, isfinite(x + y + z) ? E_ESCAPE : E_NONFINITE);
     const double ex = x - (double)xr, ey = y - (double)yr, ez = z - (double)zr;
     if (ex * ex + ey * ey + ez * ez > p.half_skin2) set_err(b, E_SKIN);
+    if (p.msum) {  // Eq. (mean_pos): this step's positions are sample s's
+      b.msx[i] += x;
+      b.msy[i] += y;
+      b.msz[i] += z;
+    }
   }
   b.vx[i] = vx;
   b.vy[i] = vy;
@@ -698,11 +721,13 @@ __global__ __launch_bounds__(kBlock) void k_force(Params p, Buffers b, int32_t k
     b.fy[i] = Fy;
     b.fz[i] = Fz;
     if (!isfinite(Fx + Fy + Fz)) set_err(b, E_NONFINITE);
-    if (g == 0) {
+    if (moves_z(p, g)) {
       double vx = b.vx[i], vy = b.vy[i], vz = b.vz[i];
       if (mode == 0) {
-        vx += p.hdt_m * Fx;
-        vy += p.hdt_m * Fy;
+        if (g == 0) {
+          vx += p.hdt_m * Fx;
+          vy += p.hdt_m * Fy;
+        }
         vz += p.hdt_m * Fz;
         b.vx[i] = vx;
         b.vy[i] = vy;
@@ -763,7 +788,7 @@ __global__ __launch_bounds__(kBlock) void k_chunk_stats(Params p, Buffers b) {
     const double x = b.x[i], y = b.y[i], z = b.z[i];
     const double c[3] = {x, y, z};
     for (int d = 0; d < 3; ++d) mn[d] = mx[d] = okey(c[d]);
-    if (g == 0) {
+    if (moves_z(p, g)) {
       const double ex = x - (double)b.xs[i], ey = y - (double)b.ys[i], ez = z - (double)b.zs[i];
       d2 = ex * ex + ey * ey + ez * ez;
       const double fx = x - (double)b.xr[i], fy = y - (double)b.yr[i], fz = z - (double)b.zr[i];
@@ -951,6 +976,11 @@ __global__ __launch_bounds__(kBlock) void k_permute(Buffers b, Buffers sc, const
   sc.group[i] = b.group[s];
   sc.orig[i] = b.orig[s];
   sc.cell[i] = key[s];
+  if (b.msx) {
+    sc.msx[i] = b.msx[s];
+    sc.msy[i] = b.msy[s];
+    sc.msz[i] = b.msz[s];
+  }
   sc.xs[i] = (float)x;
   sc.ys[i] = (float)y;
   sc.zs[i] = (float)z;
@@ -966,11 +996,11 @@ __global__ __launch_bounds__(kBlock) void k_permute(Buffers b, Buffers sc, const
 __global__ __launch_bounds__(kBlock) void k_snapshot(Buffers b, double *snap, unsigned long long *snap_slots,
                                                      double *snap_acc, int restore, int64_t ntot, int64_t nslots,
                                                      int64_t nacc) {
-  double *arr[9] = {b.x, b.y, b.z, b.vx, b.vy, b.vz, b.fx, b.fy, b.fz};
+  double *arr[12] = {b.x, b.y, b.z, b.vx, b.vy, b.vz, b.fx, b.fy, b.fz, b.msx, b.msy, b.msz};
+  const int na = b.msx ? 12 : 9;
   const int64_t stride = (int64_t)gridDim.x * kBlock;
   for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < ntot; t += stride) {
-#pragma unroll
-    for (int k = 0; k < 9; ++k) {
+    for (int k = 0; k < na; ++k) {
       if (restore) arr[k][t] = snap[k * ntot + t];
       else snap[k * ntot + t] = arr[k][t];
     }
@@ -993,6 +1023,17 @@ void launch_snapshot(const Buffers &b, double *snap, unsigned long long *snap_sl
                      nacc);
 }
 
+// v = 0 for every atom of group g (the top region is fixed again after relaxation)
+__global__ __launch_bounds__(kBlock) void k_hold_group(Buffers b, int64_t ntot, uint8_t g) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < ntot && b.group[i] == g) b.vx[i] = b.vy[i] = b.vz[i] = 0.0;
+}
+
+void launch_hold_group(const Buffers &b, int64_t ntot, int g, hipStream_t s) {
+  hipLaunchKernelGGL(k_hold_group, dim3((unsigned)((ntot + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, b, ntot,
+                     (uint8_t)g);
+}
+
 // copy the permuted arrays back into the primary buffers (one launch)
 template <class R>
 __global__ __launch_bounds__(kBlock) void k_copy_back(Buffers b, Buffers sc) {
@@ -1004,6 +1045,11 @@ __global__ __launch_bounds__(kBlock) void k_copy_back(Buffers b, Buffers sc) {
   b.group[i] = sc.group[i];
   b.orig[i] = sc.orig[i];
   b.cell[i] = sc.cell[i];
+  if (b.msx) {
+    b.msx[i] = sc.msx[i];
+    b.msy[i] = sc.msy[i];
+    b.msz[i] = sc.msz[i];
+  }
   b.xs[i] = sc.xs[i]; b.ys[i] = sc.ys[i]; b.zs[i] = sc.zs[i];
   reinterpret_cast<V4 *>(b.pos4)[i] = reinterpret_cast<const V4 *>(sc.pos4)[i];
 }
@@ -1049,7 +1095,7 @@ __global__ __launch_bounds__(kBlock) void k_count_pairs(Params p, Buffers b) {
 static inline unsigned tiles(const Params &p) { return (unsigned)(p.ntot / kTile); }
 
 void launch_burst_begin(const Params &p, const Buffers &b, int n_rep, hipStream_t s) {
-  hipLaunchKernelGGL(k_burst_begin, dim3(64), dim3(kBlock), 0, s, b, n_rep);
+  hipLaunchKernelGGL(k_burst_begin, dim3(64), dim3(kBlock), 0, s, b, n_rep, p.ntot);
 }
 
 void launch_set_base(const Buffers &b, int64_t base, hipStream_t s) {

@@ -113,6 +113,8 @@ struct Params {
   int32_t lpa;
   int32_t ktime;       // nonzero: the force kernel stamps per-block start/end times into Buffers::ktime
   int32_t conv;        // nonzero: replicas whose averages converged are skipped (Control::conv_lag > 0)
+  int32_t top_free;    // nonzero: atoms of the top region (group 2) move along z (thermal relaxation)
+  int32_t msum;        // nonzero: per-atom position sums of the burst's samples (Buffers::msx..msz)
 };
 
 // Device buffers (pointers), passed by value.
@@ -135,6 +137,7 @@ struct Buffers {
   unsigned long long *stat;   // [n_rep][kSlots][kStat]: drift^2, v^2, bbox min/max keys, list displacement^2
   double *series;      // [n_rep][series_cap][kSeriesCols]
   unsigned long long *ktime;  // [blocks][2]: device wall-clock at block start and end (timed launches)
+  double *msx, *msy, *msz;    // per-atom position sums over the burst's samples (null unless enabled)
   int64_t series_cap;
   Control *ctl;
 };
@@ -151,6 +154,7 @@ __host__ __device__ inline size_t nbr_index(int64_t i, int e, int lpa, int64_t s
 
 // ---- launch wrappers (kernels.hip) ----
 void launch_burst_begin(const Params &p, const Buffers &b, int n_rep, hipStream_t s);
+void launch_hold_group(const Buffers &b, int64_t ntot, int g, hipStream_t s);
 void launch_kick_drift(const Params &p, const Buffers &b, int precision, int32_t k, int32_t mode, hipStream_t s);
 void launch_pos4(const Params &p, const Buffers &b, int precision, hipStream_t s);
 void launch_build(const Params &p, const Buffers &b, int precision, int lpa, hipStream_t s);

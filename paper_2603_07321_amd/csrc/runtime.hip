@@ -53,7 +53,7 @@ constexpr int kMaxChunk = 256;     // steps per captured graph
 constexpr int kMinChunk = 4;
 
 struct RepHost {
-  int64_t abeg = 0, aend = 0, nreal = 0, nmob = 0;
+  int64_t abeg = 0, aend = 0, nreal = 0, nmob = 0, ntop = 0;
   int64_t orig_base = 0;  // first original index of this replica
   double T0 = 0, volume0 = 0, area0 = 0, strain = 0;
   double center[3] = {0, 0, 0};
@@ -90,7 +90,8 @@ struct ptamd_system {
   int32_t *d_key = nullptr, *d_cursor = nullptr, *d_tmp = nullptr, *d_perm = nullptr;
   int64_t cells_cap = 0;
   // snapshot for roll-back
-  double *snap = nullptr;  // 9 arrays of ntot doubles
+  double *snap = nullptr;  // 12 arrays of ntot doubles
+  bool msum_valid = false; // the position sums hold the samples of the last burst
   unsigned long long *snap_slots = nullptr;
   RepAcc *snap_acc = nullptr;
   // host staging
@@ -207,7 +208,7 @@ static void alloc_buffers(Buffers &b, int64_t ntot, int precision, bool primary)
 static void free_buffers(Buffers &b) {
   void *ptrs[] = {b.x, b.y, b.z, b.vx, b.vy, b.vz, b.fx, b.fy, b.fz, b.pos4, b.group, b.orig, b.cell,
                   b.xs, b.ys, b.zs, b.xr, b.yr, b.zr, b.nbr, b.ncount, b.cell_start, b.cell_count,
-                  b.blk_rep, b.rep, b.acc, b.slots, b.stat, b.series, b.ctl, b.ktime};
+                  b.blk_rep, b.rep, b.acc, b.slots, b.stat, b.series, b.ctl, b.ktime, b.msx, b.msy, b.msz};
   for (void *p : ptrs) dfree(p);
   b = Buffers{};
 }
@@ -220,7 +221,9 @@ static void upload_reps(ptamd_system *s) {
     std::memset(&d, 0, sizeof(d));
     d.abeg = h.abeg; d.aend = h.aend; d.nreal = h.nreal; d.nmob = h.nmob;
     d.T0 = h.T0;
-    d.dof = 3.0 * (double)h.nmob - 3.0;
+    // thermostat degrees of freedom: 3 N_mob - 3, plus one per top-region
+    // atom while that region is free along z (thermal relaxation)
+    d.dof = 3.0 * (double)h.nmob - 3.0 + (s->P.top_free ? (double)h.ntop : 0.0);
     d.volume0 = h.volume0; d.area0 = h.area0; d.strain = h.strain;
     for (int k = 0; k < 3; ++k) {
       d.origin[k] = h.origin[k];
@@ -322,6 +325,7 @@ static ptamd_system *create_from_hosts(const std::vector<HostState> &hs, const s
       double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
       for (int64_t i = 0; i < n; ++i) {
         h.nmob += hs[r].group[i] == 0;
+        h.ntop += hs[r].group[i] == 2;
         const double c[3] = {hs[r].x[i], hs[r].y[i], hs[r].z[i]};
         for (int k = 0; k < 3; ++k) {
           if (!std::isfinite(c[k])) fail(PTAMD_EINVAL, "non-finite input position");
@@ -375,7 +379,7 @@ static ptamd_system *create_from_hosts(const std::vector<HostState> &hs, const s
     s->d_key = dalloc<int32_t>(s->ntot);
     s->d_tmp = dalloc<int32_t>(s->ntot);
     s->d_perm = dalloc<int32_t>(s->ntot);
-    s->snap = dalloc<double>((size_t)9 * s->ntot);
+    s->snap = dalloc<double>((size_t)12 * s->ntot);  // x, v, F and the position sums
     s->snap_slots = dalloc<unsigned long long>((size_t)2 * s->n_rep * kSlots * kNQ);
     s->snap_acc = dalloc<RepAcc>(s->n_rep);
     HIPCHK(hipHostMalloc((void **)&s->h_ctl, sizeof(Control), 0));
@@ -526,7 +530,8 @@ static void sort_system(ptamd_system *s) {
 // ---------------------------------------------------------------------------
 // Graph of K whole steps; with_build puts a Verlet-list build in front.
 static GraphEntry &get_graph(ptamd_system *s, int K, bool with_build) {
-  const int key = 4 * K + (s->P.conv ? 2 : 0) + (with_build ? 1 : 0);
+  // every launch-time flag captured in the graph is part of its key
+  const int key = 16 * K + (s->P.msum ? 8 : 0) + (s->P.top_free ? 4 : 0) + (s->P.conv ? 2 : 0) + (with_build ? 1 : 0);
   auto it = s->graphs.find(key);
   if (it != s->graphs.end()) return it->second;
   GraphEntry g;
@@ -574,6 +579,7 @@ static void raise_err(int err) {
 // Forces at the current positions (burst start, force hook): a Verlet-list
 // build, the density pass and the force pass without the kick.
 static void initial_forces(ptamd_system *s) {
+  s->msum_valid = false;
   if (s->need_sort) sort_system(s);
   launch_burst_begin(s->P, s->B, s->n_rep, s->stream);
   launch_set_base(s->B, 0, s->stream);
@@ -784,6 +790,7 @@ static void run_burst(ptamd_system *s, int64_t n_steps, ptamd_averages *out, con
     out[r].n_samples = (int64_t)o[9];
     if (n_conv) n_conv[r] = acc[r].conv_step;
   }
+  s->msum_valid = s->P.msum != 0;
 }
 
 static void apply_strains(ptamd_system *s, const double *d_eps) {
@@ -813,6 +820,90 @@ static void apply_strains(ptamd_system *s, const double *d_eps) {
   upload_reps(s);
   s->need_sort = true;
   s->stats_valid = false;
+}
+
+// ---------------------------------------------------------------------------
+// observables beyond the burst averages
+// ---------------------------------------------------------------------------
+// Per-atom position sums over the samples of each burst (Eq. (mean_pos)),
+// allocated on first use in both the primary and the permutation buffers.
+static void set_mean_positions(ptamd_system *s, bool on) {
+  if (on == (s->P.msum != 0)) return;
+  sync(s);
+  for (Buffers *b : {&s->B, &s->S}) {
+    if (on) {
+      b->msx = dalloc<double>(s->ntot);
+      b->msy = dalloc<double>(s->ntot);
+      b->msz = dalloc<double>(s->ntot);
+    } else {
+      dfree(b->msx); dfree(b->msy); dfree(b->msz);
+      b->msx = b->msy = b->msz = nullptr;
+    }
+  }
+  s->P.msum = on ? 1 : 0;
+  s->msum_valid = false;
+  invalidate_graphs(s);
+}
+
+static void get_mean_positions(ptamd_system *s, double *x, double *y, double *z) {
+  if (!s->P.msum) fail(PTAMD_ESTATE, "mean positions are not switched on");
+  if (!s->msum_valid) fail(PTAMD_ESTATE, "no burst with mean positions since they were switched on or last cleared");
+  const int64_t N = s->ntot;
+  std::vector<RepAcc> acc(s->n_rep);
+  std::vector<int32_t> o(N);
+  std::vector<double> t(N);
+  d2h(s, acc.data(), s->B.acc, sizeof(RepAcc) * s->n_rep);
+  d2h(s, o.data(), s->B.orig, 4 * N);
+  double *dst[3] = {x, y, z};
+  double *src[3] = {s->B.msx, s->B.msy, s->B.msz};
+  for (int k = 0; k < 3; ++k) {
+    d2h(s, t.data(), src[k], 8 * N);
+    for (int r = 0; r < s->n_rep; ++r) {
+      const double n = (double)acc[r].nsamp;
+      for (int64_t i = s->reps[r].abeg; i < s->reps[r].aend; ++i)
+        if (o[i] >= 0) dst[k][o[i]] = t[i] / n;
+    }
+  }
+}
+
+// Thermal relaxation (Sec. 2.4.2): the top region moves freely along z
+// while bursts run, until the burst-averaged reaction stress of every
+// replica is below tol in magnitude, then the region is held again (v = 0).
+static void relax(ptamd_system *s, const ptamd_relax_params *rp, ptamd_averages *out, int64_t *n_bursts,
+                  int32_t *relaxed) {
+  if (rp->burst_steps < 1 || rp->max_bursts < 1) fail(PTAMD_EINVAL, "need burst_steps >= 1 and max_bursts >= 1");
+  if (!std::isfinite(rp->tol_gpa) || rp->tol_gpa < 0.0) fail(PTAMD_EINVAL, "need a finite tol_gpa >= 0");
+  for (const RepHost &h : s->reps)
+    if (h.ntop == 0) fail(PTAMD_EINVAL, "a replica has no top region to relax");
+  struct Free {
+    ptamd_system *s;
+    explicit Free(ptamd_system *q) : s(q) {
+      s->P.top_free = 1;
+      upload_reps(s);
+    }
+    ~Free() {
+      // hold the region again where it stands; nothing here may throw
+      s->P.top_free = 0;
+      launch_hold_group(s->B, s->ntot, 2, s->stream);
+      try {
+        upload_reps(s);
+        sync(s);
+      } catch (...) {
+      }
+    }
+  } free_top(s);
+  int64_t k = 0;
+  bool all = false;
+  while (!all && k < rp->max_bursts) {
+    run_burst(s, rp->burst_steps, out);
+    ++k;
+    all = true;
+    for (int r = 0; r < s->n_rep; ++r) {
+      relaxed[r] = std::fabs(out[r].tz) < rp->tol_gpa ? 1 : 0;
+      all = all && relaxed[r];
+    }
+  }
+  *n_bursts = k;
 }
 
 // state in/out in original order
@@ -1207,6 +1298,30 @@ ptamd_status ptamd_run_fast_md(ptamd_system *sys, int64_t n_steps, ptamd_average
     use_device(sys);
     if (!out) fail(PTAMD_EINVAL, "out is NULL");
     run_burst(sys, n_steps, out);
+  });
+}
+
+ptamd_status ptamd_set_mean_positions(ptamd_system *sys, int32_t enable) {
+  return guard([&] {
+    use_device(sys);
+    set_mean_positions(sys, enable != 0);
+  });
+}
+
+ptamd_status ptamd_get_mean_positions(ptamd_system *sys, double *x, double *y, double *z) {
+  return guard([&] {
+    use_device(sys);
+    if (!x || !y || !z) fail(PTAMD_EINVAL, "NULL argument");
+    get_mean_positions(sys, x, y, z);
+  });
+}
+
+ptamd_status ptamd_relax(ptamd_system *sys, const ptamd_relax_params *prm, ptamd_averages *out, int64_t *n_bursts,
+                         int32_t *relaxed) {
+  return guard([&] {
+    use_device(sys);
+    if (!prm || !out || !n_bursts || !relaxed) fail(PTAMD_EINVAL, "NULL argument");
+    relax(sys, prm, out, n_bursts, relaxed);
   });
 }
 
