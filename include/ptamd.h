@@ -144,6 +144,46 @@ ptamd_status ptamd_create_batch(int32_t n_replicas, const ptamd_lattice_desc *de
                                 const ptamd_md_params *md, ptamd_system **out);
 ptamd_status ptamd_destroy_system(ptamd_system *sys);
 
+/* ---- tabulated EAM (the setfl form of the potential of Eq. (pe)) ----
+ * The paper's runs use a tabulated aluminium EAM potential.  A table holds,
+ * for one element, F(rhobar) at rhobar = k*drho (k < nrho), rho(r) and
+ * r*phi(r) at r = k*dr (k < nr), as in a setfl file; V(r) = (r phi)(r) / r
+ * is the pair term and F the embedding term B of Eq. (pe).  Between knots
+ * each function is the not-a-knot cubic spline through its knots (the
+ * unique C2 piecewise cubic whose third derivative is also continuous at the
+ * second and the second-to-last knot); past the last knot F continues
+ * linearly with its end slope.  Pairs count for r < rc.  Requires
+ * nrho, nr >= 4, drho, dr > 0, 0 < rc <= min((nr-1) dr, 12 A), all values
+ * finite.  The atomic mass stays the library's aluminium mass. */
+typedef struct {
+    int32_t nrho;
+    double drho;
+    int32_t nr;
+    double dr;
+    double rc;
+    const double *F;     /* nrho values */
+    const double *rho;   /* nr values */
+    const double *rphi;  /* nr values: r * phi(r) */
+} ptamd_eam_table;
+
+/* Replaces the system's potential by the table (copied; the caller's arrays
+ * may be freed afterwards).  Lists and cells are rebuilt at the next call;
+ * the state is unchanged.  Every later evaluation uses the table. */
+ptamd_status ptamd_set_eam_table(ptamd_system *sys, const ptamd_eam_table *table);
+/* Reads a single-element setfl file (three comment lines; "1 <element>";
+ * "Nrho drho Nr dr cutoff"; "Z mass a0 lattice"; then F, rho and r*phi as
+ * whitespace-separated numbers).  Always sets the sizes and spacings of
+ * *table and, if mass is not NULL, the file's mass; with F, rho and rphi
+ * all non-NULL (holding nrho, nr and nr doubles) it also reads the values
+ * into them and points the table at them.  Call once to size, once to read. */
+ptamd_status ptamd_read_setfl(const char *path, ptamd_eam_table *table, double *F, double *rho, double *rphi,
+                              double *mass);
+/* The library's interpolation of one table function (which: 0 F, 1 rho,
+ * 2 r*phi) at n arguments: values f and derivatives df.  Host only, no GPU
+ * needed. */
+ptamd_status ptamd_eam_table_eval(const ptamd_eam_table *table, int32_t which, int64_t n, const double *x,
+                                  double *f, double *df);
+
 /* ---- the hot path ---- */
 /* Load step along z about z = 0 (Sec. 2.4.2 loading sequence, applied as an
  * affine strain of every atom): eps_k = eps_{k-1} + d_eps, every z scaled by

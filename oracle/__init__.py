@@ -39,9 +39,14 @@ _i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
 _i64p = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
 
 
+class TAB(C.Structure):
+    _fields_ = [("nrho", C.c_int32), ("nr", C.c_int32), ("drho", C.c_double), ("dr", C.c_double),
+                ("F", C.POINTER(C.c_double)), ("rho", C.POINTER(C.c_double)), ("rphi", C.POINTER(C.c_double))]
+
+
 class SC(C.Structure):
     _fields_ = [("eps", C.c_double), ("a", C.c_double), ("n", C.c_double), ("m", C.c_double),
-                ("c", C.c_double), ("rc", C.c_double), ("shift", C.c_int32)]
+                ("c", C.c_double), ("rc", C.c_double), ("shift", C.c_int32), ("tab", C.POINTER(TAB))]
 
 
 class MD(C.Structure):
@@ -111,6 +116,25 @@ def lib():
 
 def sc_params(eps=0.0033147, a=4.05, n=7.0, m=6.0, c=16.399, rc=8.1, shift=2) -> SC:
     return SC(eps, a, n, m, c, rc, shift)
+
+
+class TabPotential:
+    """Tabulated EAM functions for the oracle: holds the spline coefficients
+    and the SC struct (``.sc``) that points at them."""
+
+    def __init__(self, F, rho, rphi, drho: float, dr: float, rc: float):
+        from scipy.interpolate import CubicSpline  # not-a-knot cubic spline, a library step
+
+        def coef(y, h):
+            y = np.asarray(y, np.float64)
+            cs = CubicSpline(np.arange(len(y)) * h, y, bc_type="not-a-knot")
+            return np.ascontiguousarray(cs.c.T.reshape(-1))  # per interval: u^3, u^2, u, 1
+
+        self.cF, self.crho, self.crphi = coef(F, drho), coef(rho, dr), coef(rphi, dr)
+        P = C.POINTER(C.c_double)
+        self.tab = TAB(len(F), len(rho), drho, dr, self.cF.ctypes.data_as(P), self.crho.ctypes.data_as(P),
+                       self.crphi.ctypes.data_as(P))
+        self.sc = SC(0.0, 1.0, 1.0, 1.0, 0.0, rc, 0, C.pointer(self.tab))
 
 
 def md_params(dt=1.0, tau=100.0, T0=300.0, thermostat=1, top_free_z=0) -> MD:

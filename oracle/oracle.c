@@ -182,9 +182,35 @@ static double sc_dV(const orc_sc *p, double r) { return -p->n * p->eps * pow(p->
 static double sc_rho(const orc_sc *p, double r) { return pow(p->a / r, p->m); }
 static double sc_drho(const orc_sc *p, double r) { return -p->m * pow(p->a / r, p->m) / r; }
 
+/* Value and derivative of a tabulated piecewise cubic at x (knots k*h,
+ * k < n); past the last knot the end value continues with the end slope. */
+static void tab_eval(const double *c, int32_t n, double h, double x, double *f, double *df) {
+    double kk = floor(x / h);
+    if (kk < 0.0) kk = 0.0;
+    int64_t k = (int64_t)kk;
+    double u = x - (double)k * h, over = 0.0;
+    if (k > n - 2) {
+        k = n - 2;
+        u = h;
+        over = x - (double)(n - 1) * h;
+    }
+    const double *q = c + 4 * k;
+    *df = (3.0 * q[0] * u + 2.0 * q[1]) * u + q[2];
+    *f = ((q[0] * u + q[1]) * u + q[2]) * u + q[3] + over * *df;
+}
+
 /* V_s, dV_s/dr, rho_s, drho_s/dr at separation r.  Zero for r >= rc. */
 void orc_pair_terms(const orc_sc *p, double r, double *V, double *dV, double *rho, double *drho) {
     if (!(r < p->rc)) { *V = *dV = *rho = *drho = 0.0; return; }
+    if (p->tab) {
+        const orc_tab *t = p->tab;
+        double rp, drp;
+        tab_eval(t->rho, t->nr, t->dr, r, rho, drho);
+        tab_eval(t->rphi, t->nr, t->dr, r, &rp, &drp);
+        *V = rp / r;                 /* phi = (r phi) / r */
+        *dV = (drp - *V) / r;        /* phi' = ((r phi)' - phi) / r */
+        return;
+    }
     double v = sc_V(p, r), dv = sc_dV(p, r), q = sc_rho(p, r), dq = sc_drho(p, r);
     if (p->shift == 1) {
         v -= sc_V(p, p->rc);
@@ -201,6 +227,11 @@ void orc_pair_terms(const orc_sc *p, double r, double *V, double *dV, double *rh
 
 /* B(rhobar) = -c eps sqrt(rhobar); B(0) = 0. */
 double orc_embed(const orc_sc *p, double rhobar) {
+    if (p->tab) {
+        double f, df;
+        tab_eval(p->tab->F, p->tab->nrho, p->tab->drho, rhobar, &f, &df);
+        return f;
+    }
     if (!(rhobar > 0.0)) return 0.0;
     return -p->c * p->eps * sqrt(rhobar);
 }
@@ -208,6 +239,11 @@ double orc_embed(const orc_sc *p, double rhobar) {
 /* dB/drhobar = -c eps / (2 sqrt(rhobar)); taken as 0 at rhobar = 0 (an
  * isolated atom feels no embedding force). */
 double orc_embed_deriv(const orc_sc *p, double rhobar) {
+    if (p->tab) {
+        double f, df;
+        tab_eval(p->tab->F, p->tab->nrho, p->tab->drho, rhobar, &f, &df);
+        return df;
+    }
     if (!(rhobar > 0.0)) return 0.0;
     return -p->c * p->eps / (2.0 * sqrt(rhobar));
 }

@@ -28,9 +28,27 @@ extern "C" {
  *   V(r) = eps (a/r)^n,  rho(r) = (a/r)^m,  B(rhobar) = -c eps sqrt(rhobar).
  * shift: 0 = truncated at rc, 1 = energy-shifted, 2 = shifted-force
  * (value and slope of V and rho both vanish at rc). */
+/* Tabulated single-element EAM functions, the layout of a setfl file:
+ * F(rhobar) on knots k*drho (k < nrho), rho(r) and r*phi(r) on knots k*dr
+ * (k < nr).  Each is the piecewise cubic given by its coefficients per
+ * interval k, highest power first, in u = x - x_k:
+ *   f(x) = ((c[4k] u + c[4k+1]) u + c[4k+2]) u + c[4k+3].
+ * Past the last knot F continues linearly with its end slope. */
+typedef struct {
+    int32_t nrho, nr;
+    double drho, dr;
+    const double *F;     /* 4*(nrho-1) */
+    const double *rho;   /* 4*(nr-1) */
+    const double *rphi;  /* 4*(nr-1) */
+} orc_tab;
+
+/* With tab != NULL the functions of Eq. (pe) are the tables instead:
+ * V(r) = (r phi)(r) / r, rho(r), B = F; rc still bounds the pair sums and
+ * shift is ignored. */
 typedef struct {
     double eps, a, n, m, c, rc;
     int32_t shift;
+    const orc_tab *tab;
 } orc_sc;
 
 typedef struct {

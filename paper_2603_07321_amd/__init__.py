@@ -66,6 +66,22 @@ class ConvParams(C.Structure):
     _fields_ = [("lag", C.c_int64), ("n_max", C.c_int64), ("tol", C.c_double * 4), ("floor", C.c_double * 4)]
 
 
+class EAMTable(C.Structure):
+    _fields_ = [("nrho", C.c_int32), ("drho", C.c_double), ("nr", C.c_int32), ("dr", C.c_double),
+                ("rc", C.c_double), ("F", C.POINTER(C.c_double)), ("rho", C.POINTER(C.c_double)),
+                ("rphi", C.POINTER(C.c_double))]
+
+
+def eam_table(F, rho, rphi, drho: float, dr: float, rc: float):
+    """An EAMTable over copies of the arrays; returns (table, arrays kept alive)."""
+    arrs = [np.ascontiguousarray(a, np.float64) for a in (F, rho, rphi)]
+    P_ = C.POINTER(C.c_double)
+    t = EAMTable(len(arrs[0]), drho, len(arrs[1]), dr, rc, *[a.ctypes.data_as(P_) for a in arrs])
+    if len(arrs[2]) != len(arrs[1]):
+        raise ValueError("rho and r*phi need the same number of values")
+    return t, arrs
+
+
 class RelaxParams(C.Structure):
     _fields_ = [("burst_steps", C.c_int64), ("max_bursts", C.c_int64), ("tol_gpa", C.c_double)]
 
@@ -128,6 +144,9 @@ SIGNATURES = {
     "ptamd_apply_strain_increments": [_SYS, _P],
     "ptamd_run_fast_md": [_SYS, C.c_int64, C.POINTER(Averages)],
     "ptamd_run_until_converged": [_SYS, C.POINTER(ConvParams), C.POINTER(Averages), _P],
+    "ptamd_set_eam_table": [_SYS, C.POINTER(EAMTable)],
+    "ptamd_read_setfl": [C.c_char_p, C.POINTER(EAMTable), _P, _P, _P, _P],
+    "ptamd_eam_table_eval": [C.POINTER(EAMTable), C.c_int32, C.c_int64, _P, _P, _P],
     "ptamd_set_mean_positions": [_SYS, C.c_int32],
     "ptamd_get_mean_positions": [_SYS, _P, _P, _P],
     "ptamd_relax": [_SYS, C.POINTER(RelaxParams), C.POINTER(Averages), C.POINTER(C.c_int64), _P],
@@ -264,6 +283,32 @@ def run_until_converged(sys: int, conv: ConvParams) -> tuple:
     n_conv = np.zeros(nr, np.int64)
     _check(_lib.ptamd_run_until_converged(sys, C.byref(conv), out, _ptr(n_conv)))
     return [o.as_dict() for o in out], n_conv
+
+
+def set_eam_table(sys: int, F, rho, rphi, drho: float, dr: float, rc: float) -> None:
+    t, keep = eam_table(F, rho, rphi, drho, dr, rc)
+    _check(_lib.ptamd_set_eam_table(sys, C.byref(t)))
+    del keep
+
+
+def read_setfl(path: str) -> dict:
+    """Single-element setfl file -> dict(F, rho, rphi, drho, dr, rc, mass)."""
+    t = EAMTable()
+    mass = C.c_double()
+    _check(_lib.ptamd_read_setfl(path.encode(), C.byref(t), None, None, None, C.byref(mass)))
+    F, rho, rphi = np.zeros(t.nrho), np.zeros(t.nr), np.zeros(t.nr)
+    _check(_lib.ptamd_read_setfl(path.encode(), C.byref(t), _ptr(F), _ptr(rho), _ptr(rphi), C.byref(mass)))
+    return dict(F=F, rho=rho, rphi=rphi, drho=t.drho, dr=t.dr, rc=t.rc, mass=mass.value)
+
+
+def eam_table_eval(F, rho, rphi, drho: float, dr: float, rc: float, which: int, x) -> tuple:
+    """The library's spline of table function ``which`` (0 F, 1 rho, 2 r*phi) at x: (f, df)."""
+    t, keep = eam_table(F, rho, rphi, drho, dr, rc)
+    xa = np.ascontiguousarray(x, np.float64)
+    f, df = np.zeros_like(xa), np.zeros_like(xa)
+    _check(_lib.ptamd_eam_table_eval(C.byref(t), which, len(xa), _ptr(xa), _ptr(f), _ptr(df)))
+    del keep
+    return f, df
 
 
 def set_mean_positions(sys: int, enable: bool = True) -> None:
@@ -468,6 +513,9 @@ class System:
 
     def run_until_converged(self, conv: Optional[ConvParams] = None):
         return run_until_converged(self.h, conv if conv is not None else conv_params())
+
+    def set_eam_table(self, F, rho, rphi, drho: float, dr: float, rc: float):
+        set_eam_table(self.h, F, rho, rphi, drho, dr, rc)
 
     def set_mean_positions(self, enable: bool = True):
         set_mean_positions(self.h, enable)

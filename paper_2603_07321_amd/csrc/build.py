@@ -11,7 +11,7 @@ CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libptamd.so")
 BUILD_DIR = os.path.join(ROOT, "_build", "ptamd")
 
-SOURCES = ["kernels.hip", "runtime.hip", "lattice.cpp", "pta.cpp"]
+SOURCES = ["kernels.hip", "runtime.hip", "lattice.cpp", "pta.cpp", "eam_table.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

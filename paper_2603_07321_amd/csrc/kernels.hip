@@ -90,6 +90,32 @@ template <class R, int NM> __device__ __forceinline__ R rho_pow(R t, int m) {
 __device__ __forceinline__ float rsqrt_r(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double rsqrt_r(double x) { return rsqrt(x); }
 
+// Tabulated potential (NM = 2): interval and offset of r in the r tables.
+// Pairs have r < rc <= (nr - 1) dr; the clamp keeps rounding at the last
+// knot inside the table.
+template <class R> __device__ __forceinline__ int tab_interval(const Params &p, R r, R *t) {
+  const R sx = r * (R)p.tab_inv_dr;
+  const int k = min((int)sx, p.tab_kmax);
+  *t = sx - (R)k;
+  return k;
+}
+
+// F(rhobar) and F'(rhobar) of the tabulated embedding function (FP64); past
+// the last knot F continues linearly with its end slope.
+__device__ __forceinline__ void tab_embed(const Params &p, const double *cF, double rb, double *F, double *dF) {
+  const double sx = rb * p.tab_inv_drho;
+  int k = (int)sx;
+  double t = sx - (double)k, over = 0.0;
+  if (k > p.tab_nrho - 2) {
+    k = p.tab_nrho - 2;
+    t = 1.0;
+    over = (sx - (double)(p.tab_nrho - 1)) / p.tab_inv_drho;
+  }
+  const double *c = cF + 4 * (size_t)k;
+  *dF = (c[1] + t * (2.0 * c[2] + 3.0 * t * c[3])) * p.tab_inv_drho;
+  *F = c[0] + t * (c[1] + t * (c[2] + t * c[3])) + over * *dF;
+}
+
 // Sum NQ int64 values over the block and add the totals into one slot row.
 template <int NQ>
 __device__ __forceinline__ void block_slot_add(long long (&v)[NQ], unsigned long long *row) {
@@ -619,7 +645,14 @@ __global__ __launch_bounds__(kBlock) void k_density(Params p, Buffers b, int32_t
         if (u < rem && r2 < rc2) {
           const R rinv = rsqrt_r(r2);
           const R rr = r2 * rinv;
-          acc += rho_pow<R, NM>(a * rinv, p.m) - rhoc - (rr - rc) * drhoc;
+          if (NM == 2) {
+            R t;
+            const int kk = tab_interval<R>(p, rr, &t);
+            const V4 c = reinterpret_cast<const V4 *>(b.tab_r)[2 * kk];
+            acc += c.x + t * (c.y + t * (c.z + t * c.w));
+          } else {
+            acc += rho_pow<R, NM>(a * rinv, p.m) - rhoc - (rr - rc) * drhoc;
+          }
         }
       }
     }
@@ -630,7 +663,9 @@ __global__ __launch_bounds__(kBlock) void k_density(Params p, Buffers b, int32_t
   if (lane == 0 && real) {
     const double rb = (double)acc;
     double Bp = 0.0, B = 0.0;
-    if (rb > 0.0) {
+    if (NM == 2) {
+      tab_embed(p, b.tab_F, rb, &B, &Bp);
+    } else if (rb > 0.0) {
       const double sq = sqrt(rb);
       B = -p.c_eps * sq;
       Bp = -0.5 * p.c_eps / sq;
@@ -687,13 +722,28 @@ __global__ __launch_bounds__(kBlock) void k_force(Params p, Buffers b, int32_t k
         if (u < rem && r2 < rc2) {
           const R rinv = rsqrt_r(r2);
           const R rr = r2 * rinv;
-          R tn, tm;
-          sc_powers<R, NM>(a * rinv, p.n, p.m, &tn, &tm);
-          const R V = eps * tn;
-          const R dV = -nn * V * rinv;
-          const R drho = -mm * tm * rinv;
-          const R Vs = V - Vc - (rr - rc) * dVc;
-          const R gg = (dV - dVc) + (pi.w + pj[u].w) * (drho - drhoc);
+          R Vs, gg;
+          if (NM == 2) {
+            // setfl tables: V = (r phi)/r, V' = ((r phi)' - V)/r, rho' from its spline
+            R t;
+            const int kk = tab_interval<R>(p, rr, &t);
+            const V4 cr = reinterpret_cast<const V4 *>(b.tab_r)[2 * kk];
+            const V4 cp = reinterpret_cast<const V4 *>(b.tab_r)[2 * kk + 1];
+            const R idr = (R)p.tab_inv_dr;
+            const R drho = (cr.y + t * ((R)2 * cr.z + (R)3 * t * cr.w)) * idr;
+            const R rphi = cp.x + t * (cp.y + t * (cp.z + t * cp.w));
+            const R drphi = (cp.y + t * ((R)2 * cp.z + (R)3 * t * cp.w)) * idr;
+            Vs = rphi * rinv;
+            gg = (drphi - Vs) * rinv + (pi.w + pj[u].w) * drho;
+          } else {
+            R tn, tm;
+            sc_powers<R, NM>(a * rinv, p.n, p.m, &tn, &tm);
+            const R V = eps * tn;
+            const R dV = -nn * V * rinv;
+            const R drho = -mm * tm * rinv;
+            Vs = V - Vc - (rr - rc) * dVc;
+            gg = (dV - dVc) + (pi.w + pj[u].w) * (drho - drhoc);
+          }
           const R f = gg * rinv;
           fx += f * dx;
           fy += f * dy;
@@ -1147,6 +1197,8 @@ static void force_lpa(const Params &p, const Buffers &b, int lpa, int32_t k, int
 }
 
 static bool is_al76(const Params &p) { return p.n == 7 && p.m == 6; }
+// kernel form of the potential: 2 tables, 1 Sutton-Chen n = 7 / m = 6, 0 any Sutton-Chen
+static int pot_form(const Params &p) { return p.tab ? 2 : (is_al76(p) ? 1 : 0); }
 
 template <class R>
 static void build_lpa(const Params &p, const Buffers &b, int lpa, hipStream_t s) {
@@ -1166,16 +1218,26 @@ void launch_build(const Params &p, const Buffers &b, int precision, int lpa, hip
 }
 
 void launch_density(const Params &p, const Buffers &b, int precision, int lpa, int32_t k, hipStream_t s) {
-  const bool f = is_al76(p);
-  if (precision) f ? density_lpa<float, 1>(p, b, lpa, k, s) : density_lpa<float, 0>(p, b, lpa, k, s);
-  else f ? density_lpa<double, 1>(p, b, lpa, k, s) : density_lpa<double, 0>(p, b, lpa, k, s);
+  switch (pot_form(p) + 3 * (precision ? 1 : 0)) {
+    case 0: density_lpa<double, 0>(p, b, lpa, k, s); break;
+    case 1: density_lpa<double, 1>(p, b, lpa, k, s); break;
+    case 2: density_lpa<double, 2>(p, b, lpa, k, s); break;
+    case 3: density_lpa<float, 0>(p, b, lpa, k, s); break;
+    case 4: density_lpa<float, 1>(p, b, lpa, k, s); break;
+    default: density_lpa<float, 2>(p, b, lpa, k, s); break;
+  }
 }
 
 void launch_force(const Params &p, const Buffers &b, int precision, int lpa, int32_t k, int32_t mode,
                   hipStream_t s) {
-  const bool f = is_al76(p);
-  if (precision) f ? force_lpa<float, 1>(p, b, lpa, k, mode, s) : force_lpa<float, 0>(p, b, lpa, k, mode, s);
-  else f ? force_lpa<double, 1>(p, b, lpa, k, mode, s) : force_lpa<double, 0>(p, b, lpa, k, mode, s);
+  switch (pot_form(p) + 3 * (precision ? 1 : 0)) {
+    case 0: force_lpa<double, 0>(p, b, lpa, k, mode, s); break;
+    case 1: force_lpa<double, 1>(p, b, lpa, k, mode, s); break;
+    case 2: force_lpa<double, 2>(p, b, lpa, k, mode, s); break;
+    case 3: force_lpa<float, 0>(p, b, lpa, k, mode, s); break;
+    case 4: force_lpa<float, 1>(p, b, lpa, k, mode, s); break;
+    default: force_lpa<float, 2>(p, b, lpa, k, mode, s); break;
+  }
 }
 
 void launch_chunk_stats(const Params &p, const Buffers &b, hipStream_t s) {

@@ -115,6 +115,13 @@ struct Params {
   int32_t conv;        // nonzero: replicas whose averages converged are skipped (Control::conv_lag > 0)
   int32_t top_free;    // nonzero: atoms of the top region (group 2) move along z (thermal relaxation)
   int32_t msum;        // nonzero: per-atom position sums of the burst's samples (Buffers::msx..msz)
+  // tabulated potential (setfl form; used when tab != 0 instead of the Sutton-Chen functions)
+  int32_t tab;
+  int32_t tab_kmax;    // last interval of the r tables (nr - 2)
+  double tab_inv_dr;   // 1 / dr
+  double tab_inv_drho; // 1 / drho
+  int32_t tab_nrho;
+  int32_t pad3;
 };
 
 // Device buffers (pointers), passed by value.
@@ -138,6 +145,8 @@ struct Buffers {
   double *series;      // [n_rep][series_cap][kSeriesCols]
   unsigned long long *ktime;  // [blocks][2]: device wall-clock at block start and end (timed launches)
   double *msx, *msy, *msz;    // per-atom position sums over the burst's samples (null unless enabled)
+  void *tab_r;     // per r interval: spline coefficients (a, b, c, d) of rho, then of r*phi (R precision)
+  double *tab_F;   // per rhobar interval: (a, b, c, d) of F (FP64)
   int64_t series_cap;
   Control *ctl;
 };

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "../../include/ptamd.h"
+#include "eam_table.h"
 #include "lattice.h"
 #include "ptamd_internal.h"
 
@@ -208,7 +209,8 @@ static void alloc_buffers(Buffers &b, int64_t ntot, int precision, bool primary)
 static void free_buffers(Buffers &b) {
   void *ptrs[] = {b.x, b.y, b.z, b.vx, b.vy, b.vz, b.fx, b.fy, b.fz, b.pos4, b.group, b.orig, b.cell,
                   b.xs, b.ys, b.zs, b.xr, b.yr, b.zr, b.nbr, b.ncount, b.cell_start, b.cell_count,
-                  b.blk_rep, b.rep, b.acc, b.slots, b.stat, b.series, b.ctl, b.ktime, b.msx, b.msy, b.msz};
+                  b.blk_rep, b.rep, b.acc, b.slots, b.stat, b.series, b.ctl, b.ktime, b.msx, b.msy, b.msz,
+                  b.tab_r, b.tab_F};
   for (void *p : ptrs) dfree(p);
   b = Buffers{};
 }
@@ -906,6 +908,57 @@ static void relax(ptamd_system *s, const ptamd_relax_params *rp, ptamd_averages 
   *n_bursts = k;
 }
 
+// Tabulated potential: spline coefficients of the three setfl functions,
+// uploaded once; the r tables interleave rho and r*phi per interval so that
+// one pair reads both from one 32- (FP32) or 64-byte (FP64) run.
+static void set_eam_table(ptamd_system *s, const ptamd_eam_table *t) {
+  const char *why = check_table(t);
+  if (*why) fail(PTAMD_EINVAL, why);
+  std::vector<double> cr, cp, cf;
+  spline_coefficients(t->rho, t->nr, t->dr, cr);
+  spline_coefficients(t->rphi, t->nr, t->dr, cp);
+  spline_coefficients(t->F, t->nrho, t->drho, cf);
+  const size_t nint = (size_t)t->nr - 1;
+  std::vector<double> rr(8 * nint);
+  for (size_t k = 0; k < nint; ++k)
+    for (int q = 0; q < 4; ++q) {
+      rr[8 * k + q] = cr[4 * k + q];
+      rr[8 * k + 4 + q] = cp[4 * k + q];
+    }
+  sync(s);
+  Buffers &B = s->B;
+  dfree(B.tab_r);
+  dfree(B.tab_F);
+  B.tab_r = nullptr;
+  B.tab_F = nullptr;
+  if (s->precision) {
+    std::vector<float> rf(rr.begin(), rr.end());
+    B.tab_r = dalloc<float>(rf.size());
+    h2d(s, B.tab_r, rf.data(), 4 * rf.size());
+  } else {
+    B.tab_r = dalloc<double>(rr.size());
+    h2d(s, B.tab_r, rr.data(), 8 * rr.size());
+  }
+  B.tab_F = dalloc<double>(cf.size());
+  h2d(s, B.tab_F, cf.data(), 8 * cf.size());
+  Params &P = s->P;
+  P.tab = 1;
+  P.tab_kmax = t->nr - 2;
+  P.tab_inv_dr = 1.0 / t->dr;
+  P.tab_inv_drho = 1.0 / t->drho;
+  P.tab_nrho = t->nrho;
+  s->sc.rc = t->rc;
+  P.rc = t->rc;
+  P.rc2 = t->rc * t->rc;
+  P.Vc = P.dVc = P.rhoc = P.drhoc = 0.0;
+  set_list_geometry(s);
+  alloc_list(s, list_capacity_guess(s));
+  invalidate_graphs(s);
+  s->need_sort = true;
+  s->need_build = true;
+  s->stats_valid = false;
+}
+
 // state in/out in original order
 static void get_state(ptamd_system *s, double *x, double *y, double *z, double *vx, double *vy, double *vz) {
   const int64_t N = s->ntot;
@@ -1083,7 +1136,8 @@ static void autotune(ptamd_system *s, int64_t probe_steps, int use_cache, int *o
                      double *out_ms) {
   if (probe_steps < 10) fail(PTAMD_EINVAL, "probe_steps must be >= 10");
   char keyb[128];
-  std::snprintf(keyb, sizeof keyb, "n%lld-r%d-p%d-rc%.4f", (long long)s->nreal, s->n_rep, s->precision, s->sc.rc);
+  std::snprintf(keyb, sizeof keyb, "n%lld-r%d-p%d-rc%.4f-t%d", (long long)s->nreal, s->n_rep, s->precision, s->sc.rc,
+                s->P.tab);
   const std::string key(keyb);
   if (use_cache) {
     auto it = g_tune_cache.find(key);
@@ -1298,6 +1352,13 @@ ptamd_status ptamd_run_fast_md(ptamd_system *sys, int64_t n_steps, ptamd_average
     use_device(sys);
     if (!out) fail(PTAMD_EINVAL, "out is NULL");
     run_burst(sys, n_steps, out);
+  });
+}
+
+ptamd_status ptamd_set_eam_table(ptamd_system *sys, const ptamd_eam_table *table) {
+  return guard([&] {
+    use_device(sys);
+    set_eam_table(sys, table);
   });
 }
 

@@ -1,0 +1,123 @@
+"""Tabulated EAM (setfl form) on the GPU, through the C ABI, against the
+oracle evaluating the same tables.
+
+Bars: FP64 forces |dF| <= 1e-9 max(|F|, F_rms), energy 1e-10 eV/atom,
+100-step trajectories |dr| <= 1e-8 A; mixed forces 2e-4 (FP32 coefficients
+and interpolation), energy 1e-5 eV/atom.  Tabulated against analytic
+Sutton-Chen on the GPU: within the spline's interpolation error (1e-7 F_rms
+at dr = 2e-3 A).
+"""
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from test_oracle_eam_table import sc_tables
+
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_2603_07321_amd")
+
+
+def _orc():
+    import oracle
+    return oracle
+
+
+@pytest.fixture(scope="module")
+def tables():
+    return sc_tables(_orc(), nr=4001, nrho=4001)
+
+
+def _state(nc, noise, T0, seed):
+    O = _orc()
+    s = synth.cube_state(nc, noise, 0.0, seed)
+    vx, vy, vz = O.mb_velocities(s["group"], T0, seed)
+    s.update(vx=vx, vy=vy, vz=vz)
+    return s
+
+
+def _ferr(G, F):
+    frms = np.sqrt((F ** 2).sum(1).mean())
+    return (np.linalg.norm(G - F, axis=1) / np.maximum(np.linalg.norm(F, axis=1), frms)).max()
+
+
+@pytest.mark.parametrize("precision,lpa", [(0, 4), (0, 1), (1, 4), (1, 16)])
+def test_tabulated_forces_match_oracle(tables, precision, lpa):
+    O = _orc()
+    s = _state(5, 0.1, 300.0, 71)
+    T = O.TabPotential(*tables)
+    ref = O.forces(s["x"], s["y"], s["z"], T.sc, s["group"])
+    F = np.stack([ref["fx"], ref["fy"], ref["fz"]], 1)
+    md = P.md_params(precision=precision, lanes_per_atom=lpa)
+    with P.System.from_state(s, T0=300.0, md=md) as g:
+        g.set_eam_table(*tables)
+        f = g.compute_forces()
+    G = np.stack([f["fx"], f["fy"], f["fz"]], 1)
+    err = _ferr(G, F)
+    du = abs(f["U"][0] - ref["U"]) / len(G)
+    print(f"\nprecision {precision} lpa {lpa}: force {err:.2e}, U/atom {du:.2e}")
+    if precision == 0:
+        assert err <= 1e-9 and du <= 1e-10
+        assert f["Wzz"][0] == pytest.approx(ref["Wzz"], rel=1e-9)
+    else:
+        assert err <= 2e-4 and du <= 1e-5
+
+
+def test_tabulated_trajectory_matches_oracle(tables):
+    O = _orc()
+    s = _state(5, 0.05, 300.0, 72)
+    T = O.TabPotential(*tables)
+    with P.System.from_state(s, T0=300.0, md=P.md_params(precision=0, lanes_per_atom=4)) as g:
+        g.set_eam_table(*tables)
+        g.apply_strain_increment(1e-4)
+        avg = g.run_fast_md(100)[0]
+        st = g.get_state()
+    os_ = O.State(*(s[k].copy() for k in ("x", "y", "z", "vx", "vy", "vz", "group")), s["volume0"], s["area0"])
+    O.apply_strain(os_, 1e-4)
+    ravg, _ = O.run_burst(os_, T.sc, O.md_params(), 100)
+    dr = max(np.abs(st[k] - getattr(os_, k)).max() for k in ("x", "y", "z"))
+    print(f"\ntabulated FP64 100 steps: |dr| {dr:.2e}")
+    assert dr <= 1e-8
+    for k in ("ke", "pe", "szz", "tz"):
+        assert avg[k] == pytest.approx(ravg[k], rel=1e-9, abs=1e-9), k
+
+
+def test_tabulated_close_to_analytic_on_gpu(tables):
+    s = _state(6, 0.1, 300.0, 73)
+    md = P.md_params(precision=0, lanes_per_atom=4)
+    with P.System.from_state(s, T0=300.0, md=md) as g:
+        a = g.compute_forces()
+        g.set_eam_table(*tables)
+        t = g.compute_forces()
+    A = np.stack([a["fx"], a["fy"], a["fz"]], 1)
+    B = np.stack([t["fx"], t["fy"], t["fz"]], 1)
+    frms = np.sqrt((A ** 2).sum(1).mean())
+    print(f"\ntabulated vs analytic: {np.abs(A - B).max() / frms:.2e} of F_rms")
+    assert np.abs(A - B).max() <= 1e-7 * frms
+    assert t["U"][0] == pytest.approx(a["U"][0], rel=1e-10)
+
+
+def test_setfl_file_drives_the_gpu(tables, tmp_path):
+    from test_eam_table_host import _write_setfl
+    path = os.path.join(tmp_path, "sc.setfl")
+    _write_setfl(path, *tables)
+    t = P.read_setfl(path)
+    s = _state(4, 0.05, 300.0, 74)
+    md = P.md_params(precision=1, lanes_per_atom=4)
+    out = []
+    for src in (tables, (t["F"], t["rho"], t["rphi"], t["drho"], t["dr"], t["rc"])):
+        with P.System.from_state(s, T0=300.0, md=md) as g:
+            g.set_eam_table(*src)
+            out.append(g.run_fast_md(50)[0])
+    assert out[0] == out[1]
+
+
+def test_tabulated_batch_runs_and_converges(tables):
+    descs = [P.lattice_desc(4, 250.0, 5), P.lattice_desc(5, 350.0, 6)]
+    with P.System.batch(descs, md=P.md_params(precision=1)) as b:
+        b.set_eam_table(*tables)
+        avg, ns = b.run_until_converged(P.conv_params(50, 1000, (0.01, 0.01, 0, 0)))
+    for a in avg:
+        assert np.isfinite(a["pe"]) and a["n_samples"] > 0
