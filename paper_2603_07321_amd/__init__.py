@@ -18,7 +18,9 @@ from typing import Optional, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libptamd.so")
+# PTAMD_LIBRARY may name another build of the library (e.g. a variant built
+# for comparison); by default the in-tree build is loaded.
+LIB_PATH = os.environ.get("PTAMD_LIBRARY") or os.path.join(_HERE, "libptamd.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() (hipcc, gfx950)")

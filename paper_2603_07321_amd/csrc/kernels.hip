@@ -90,6 +90,51 @@ template <class R, int NM> __device__ __forceinline__ R rho_pow(R t, int m) {
 __device__ __forceinline__ float rsqrt_r(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double rsqrt_r(double x) { return rsqrt(x); }
 
+// Slots per lane of an atom with cnt list entries, padded to whole passes.
+template <int LPA> __device__ __forceinline__ int pass_slots(int cnt) {
+  return (cnt + kPass * LPA - 1) / (kPass * LPA) * kPass;
+}
+
+// Gather of one position entry: a uniform base plus a 32-bit byte offset
+// (the global-load form with a scalar base), one shift per gather instead of
+// 64-bit address arithmetic.  Indices stay below 2^27 (checked at creation).
+template <class V4> __device__ __forceinline__ V4 gather(const V4 *base, int j) {
+  const unsigned off = (unsigned)j * (unsigned)sizeof(V4);
+  return *reinterpret_cast<const V4 *>(reinterpret_cast<const char *>(base) + off);
+}
+
+template <class V4>
+__device__ __forceinline__ void gather8(const V4 *p4, int4 la, int4 lb, V4 (&pj)[8]) {
+  const int jv[8] = {la.x, la.y, la.z, la.w, lb.x, lb.y, lb.z, lb.w};
+#pragma unroll
+  for (int u = 0; u < 8; ++u) pj[u] = gather<V4>(p4, jv[u]);
+}
+
+// One lane's walk over its padded list: passes of eight entries (two int4
+// groups, eight independent gathers in flight).  The list entries of the
+// next pass are loaded right after the current pass's gathers: loads return
+// in order, so the arithmetic's waits for this pass's gathers never wait for
+// them, and their latency (the list streams from HBM or the Infinity Cache)
+// hides behind this pass's arithmetic.  The scheduling barriers keep that
+// issue order.  (Gathering the next pass's positions ahead as well, into a
+// second buffer, measured slower on the 62,500-atom cube.)  body(pj)
+// evaluates eight gathered entries.
+template <class V4, class Body>
+__device__ __forceinline__ void pair_passes(const V4 *p4, const int4 *nb4, int64_t stride, int npl, Body &&body) {
+  int4 la = nb4[0], lb = nb4[stride];
+  V4 pj[8];
+  for (int s = 0; s < npl; s += kPass) {
+    gather8(p4, la, lb, pj);
+    __builtin_amdgcn_sched_barrier(0);
+    if (s + kPass < npl) {
+      la = nb4[(size_t)((s + kPass) / kGroup) * stride];
+      lb = nb4[(size_t)((s + kPass) / kGroup + 1) * stride];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    body(pj);
+  }
+}
+
 // Tabulated potential (NM = 2): interval and offset of r in the r tables.
 // Pairs have r < rc <= (nr - 1) dr; the clamp keeps rounding at the last
 // knot inside the table.
@@ -220,10 +265,10 @@ __device__ void sample_values(const Params &p, const RepInfo &rp, const double *
 __device__ __forceinline__ int sum_col(int c) { return c == 3 ? 5 : c; }
 
 // Sample s (1-based) of replica r: running sums, batch sums, series row.
-__device__ void record_sample(const Params &p, const Buffers &b, int r, int64_t s, const double *q, double lam) {
-  RepAcc &A = b.acc[r];
+__device__ void record_sample(const Params &p, const Buffers &b, const Control &c, const RepInfo &rp, RepAcc &A,
+                              int r, int64_t s, const double *q, double lam) {
   double m[5];
-  sample_values(p, b.rep[r], q, lam, m);
+  sample_values(p, rp, q, lam, m);
   const double *S0 = A.sum[(s - 1) & 1];
   double *S1 = A.sum[s & 1];
   S1[0] = S0[0] + m[0];
@@ -232,11 +277,11 @@ __device__ void record_sample(const Params &p, const Buffers &b, int r, int64_t 
   S1[3] = S0[3] + m[4];
   S1[4] = S0[4] + lam;
   S1[5] = S0[5] + m[3];
-  const int64_t bs0 = b.ctl->se_block;
+  const int64_t bs0 = c.se_block;
   if (bs0 > 0) {
     int64_t bs = A.se_bs > 0 ? A.se_bs : bs0;
     int64_t bi = A.nsamp / bs;
-    if (b.ctl->conv_lag > 0 && bi >= kSEBlocks) {
+    if (c.conv_lag > 0 && bi >= kSEBlocks) {
       // open-ended run: merge neighbouring batches, doubling their length
       for (int j = 0; j < kSEBlocks / 2; ++j)
         for (int c = 0; c < 3; ++c) A.blk[j][c] = A.blk[2 * j][c] + A.blk[2 * j + 1][c];
@@ -286,8 +331,7 @@ __device__ bool averages_converged(const Buffers &b, int r, int64_t i, int64_t l
 
 // Averages over the samples so far; batch standard errors from the complete
 // batches (20 of n / 20 for a fixed-length burst, 10 to 20 for an open-ended one).
-__device__ void write_averages(const Buffers &b, int r) {
-  RepAcc &A = b.acc[r];
+__device__ void write_averages(const Control &c, const RepInfo &rp, RepAcc &A) {
   const double n = (double)A.nsamp;
   const double *S = A.sum[A.nsamp & 1];
   A.out[0] = S[0] / n;
@@ -296,7 +340,7 @@ __device__ void write_averages(const Buffers &b, int r) {
   A.out[3] = S[5] / n;
   const int64_t bs = A.se_bs;
   int64_t nb = 0;
-  if (bs > 0) nb = (b.ctl->conv_lag > 0) ? min((int64_t)kSEBlocks, A.nsamp / bs) : (int64_t)kSEBlocks;
+  if (bs > 0) nb = (c.conv_lag > 0) ? min((int64_t)kSEBlocks, A.nsamp / bs) : (int64_t)kSEBlocks;
   for (int q = 0; q < 3; ++q) {
     double se = NAN;
     if (nb >= 2) {
@@ -313,7 +357,7 @@ __device__ void write_averages(const Buffers &b, int r) {
     A.out[4 + q] = se;
   }
   A.out[7] = S[3] / n;
-  A.out[8] = b.rep[r].strain;
+  A.out[8] = rp.strain;
   A.out[9] = n;
 }
 
@@ -340,48 +384,92 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(Params p, Buffers b, int3
     xr = b.xr[i]; yr = b.yr[i]; zr = b.zr[i];
   }
   const int64_t step = b.ctl->base + k;  // mode 0: step being computed; mode 1: n_steps + 1
-  // a replica whose running averages converged stays frozen for the rest of
-  // the burst (the whole block leaves together)
-  if (p.conv && b.acc[r].conv_step != 0) return;
+  // A replica whose running averages converged in an earlier launch stays
+  // frozen (the whole block leaves together).  One that converges in this
+  // launch (at sample step - 1, written by its first block while others may
+  // still be starting) still takes this launch's lambda.
+  if (p.conv) {
+    const int64_t cs = b.acc[r].conv_step;
+    if (cs != 0 && cs < step - 1) return;
+  }
   __shared__ double s_lam;
   __shared__ int s_stop;
+  // While the first wavefront reduces the slots, the second stages in LDS
+  // what thread 0 needs afterwards: the replica's data, the control block
+  // and, in the replica's first block (which records the sample), the
+  // accumulators.  Thread 0 then works from LDS instead of a chain of
+  // dependent global loads; the accumulators go back at the end.
+  __shared__ RepAcc s_acc;
+  __shared__ RepInfo s_rep;
+  __shared__ Control s_ctl;
+  const bool first = p.n_rep == 1 ? tile == 0 : (tile == 0 || b.blk_rep[tile - 1] != r);
+  constexpr int kAccWords = (int)(sizeof(RepAcc) / sizeof(double));
+  constexpr int kRepWords = (int)(sizeof(RepInfo) / sizeof(double));
+  constexpr int kCtlWords = (int)(sizeof(Control) / sizeof(double));
+  static_assert(sizeof(RepAcc) % 8 == 0 && sizeof(RepInfo) % 8 == 0 && sizeof(Control) % 8 == 0, "word copies");
+  static_assert(kRepWords <= 64 && kCtlWords <= 64, "one word per lane of the staging wavefront");
+  if (threadIdx.x >= 64 && threadIdx.x < 128) {
+    const int t = (int)threadIdx.x - 64;
+    if (t < kRepWords) reinterpret_cast<double *>(&s_rep)[t] = reinterpret_cast<const double *>(&b.rep[r])[t];
+    if (t < kCtlWords) reinterpret_cast<double *>(&s_ctl)[t] = reinterpret_cast<const double *>(b.ctl)[t];
+    if (first) {
+      const double *src = reinterpret_cast<const double *>(&b.acc[r]);
+      double *dst = reinterpret_cast<double *>(&s_acc);
+      for (int u = t; u < kAccWords; u += 64) dst[u] = src[u];
+    }
+  }
+  long long q[6];
   if (threadIdx.x < 64) {
-    // both parities' rows are loaded before the step index arrives
+    // lambda needs only the kinetic sum (Q_MV2, slot column 0); the sample's
+    // other sums are reduced by the replica's first block, and by every
+    // block at a convergence check (all of them take that decision)
+    // Both parities' rows are loaded before the step index arrives.
     const unsigned long long *row0 = slot_row(b, p.n_rep, 0, r, threadIdx.x);
     const unsigned long long *row1 = slot_row(b, p.n_rep, 1, r, threadIdx.x);
-    long long q0[6], q1[6], q[6];
-#pragma unroll
-    for (int t = 0; t < 6; ++t) {
-      q0[t] = (long long)row0[t];
-      q1[t] = (long long)row1[t];
-    }
+    long long q0[6] = {0, 0, 0, 0, 0, 0}, q1[6] = {0, 0, 0, 0, 0, 0};
+    q0[Q_MV2] = (long long)row0[Q_MV2];
+    q1[Q_MV2] = (long long)row1[Q_MV2];
+    if (first)
+      for (int t = 1; t < 6; ++t) {
+        q0[t] = (long long)row0[t];
+        q1[t] = (long long)row1[t];
+      }
     const bool odd = ((step - 1) & 1) != 0;
+    const int64_t lag0 = p.conv ? b.ctl->conv_lag : 0;
+    const bool check = lag0 > 0 && (step - 1) % lag0 == 0;
+    if (check && !first)
+      for (int t = 1; t < 6; ++t) {
+        q0[t] = (long long)row0[t];
+        q1[t] = (long long)row1[t];
+      }
+    const int nq = (first || check) ? 6 : 1;
 #pragma unroll
     for (int t = 0; t < 6; ++t) q[t] = (step > 1) ? (odd ? q1[t] : q0[t]) : 0;
-    if (step > 1) {
-#pragma unroll
-      for (int t = 0; t < 6; ++t)
+    if (step > 1)
+      for (int t = 0; t < nq; ++t)
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) q[t] += shfl_xor_ll(q[t], o);
-    }
+  }
+  __syncthreads();  // the staged copies are in LDS
+  {
     if (threadIdx.x == 0) {
       double lam = 1.0;
       int stop = 0;
       if (step > 1) {
         double qd[6];
         for (int t = 0; t < 6; ++t) qd[t] = (double)q[t] / kFix;
-        const RepInfo &rp = b.rep[r];
+        const RepInfo &rp = s_rep;
         if (p.thermostat) {
           const double T = qd[Q_MV2] / (rp.dof * p.kb);
           const double l2 = 1.0 + (p.dt / p.tau) * (rp.T0 / T - 1.0);
           if (!(T > 0.0) || !(l2 >= 0.0)) {
-            if (tile == rp.abeg / kTile) set_err(b, E_STATE);
+            if (first) set_err(b, E_STATE);
           } else {
             lam = sqrt(l2);
           }
         }
         const int64_t smp = step - 1;  // the sample this launch completes
-        const int64_t lag = p.conv ? b.ctl->conv_lag : 0;
+        const int64_t lag = p.conv ? s_ctl.conv_lag : 0;
         const bool check = lag > 0 && smp % lag == 0;
         if (check && smp >= 2 * lag) {
           // every block of the replica takes the same decision from the same data
@@ -389,16 +477,16 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(Params p, Buffers b, int3
           sample_values(p, rp, qd, lam, m);
           stop = averages_converged(b, r, smp, lag, m) ? 1 : 0;
         }
-        if (tile == rp.abeg / kTile) {
-          record_sample(p, b, r, smp, qd, lam);
-          RepAcc &A = b.acc[r];
+        if (first) {
+          RepAcc &A = s_acc;
+          record_sample(p, b, s_ctl, rp, A, r, smp, qd, lam);
           if (check) {
             const double *S = A.sum[smp & 1];
             double *C = A.csum[(smp / lag) & 1];
             for (int f = 0; f < 4; ++f) C[f] = S[sum_col(f)];
           }
           if (stop) A.conv_step = smp;
-          if (stop || mode == 1) write_averages(b, r);
+          if (stop || mode == 1) write_averages(s_ctl, rp, A);
         }
       }
       s_lam = lam;
@@ -406,6 +494,11 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(Params p, Buffers b, int3
     }
   }
   __syncthreads();
+  if (first && step > 1 && threadIdx.x >= 64 && threadIdx.x < 128) {
+    const double *src = reinterpret_cast<const double *>(&s_acc);
+    double *dst = reinterpret_cast<double *>(&b.acc[r]);
+    for (int t = (int)threadIdx.x - 64; t < kAccWords; t += 64) dst[t] = src[t];
+  }
   const bool step_on = mode == 0 && !s_stop;
   if (!mob) {  // fixed or padding atom: v = 0, never moves
     if (p.msum && step_on && grp != kPad) {
@@ -437,8 +530,7 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(Params p, Buffers b, int3
     v4.z = (R)z;
     v4.w = (R)0;
     reinterpret_cast<V4 *>(b.pos4)[i] = v4;
-    const RepInfo &rp = b.rep[r];
-    const double cx = x - rp.center[0], cy = y - rp.center[1], cz = z - rp.center[2];
+    const double cx = x - s_rep.center[0], cy = y - s_rep.center[1], cz = z - s_rep.center[2];
     if (!(cx * cx + cy * cy + cz * cz <= p.esc2)) set_err(b, isfinite(x + y + z) ? E_ESCAPE : E_NONFINITE);
     const double ex = x - (double)xr, ey = y - (double)yr, ez = z - (double)zr;
     if (ex * ex + ey * ey + ez * ez > p.half_skin2) set_err(b, E_SKIN);
@@ -579,11 +671,13 @@ __device__ void build_one(const Params &p, const Buffers &b, int64_t i, int lane
       }
     }
   }
+  const bool over = cnt > cap;  // cnt is the same in all KB lanes (ballot counts)
+  if (over) cnt = cap;
+  // pad to whole passes with the sentinel (cap is a multiple of kPass * LPA)
+  const int padded = (cnt + kPass * LPA - 1) / (kPass * LPA) * (kPass * LPA);
+  for (int e = cnt + lane; e < padded; e += KB) b.nbr[nbr_index(i, e, LPA, p.nbr_stride)] = (int)p.ntot;
   if (lane == 0) {
-    if (cnt > cap) {
-      set_err(b, E_OVERFLOW);
-      cnt = cap;
-    }
+    if (over) set_err(b, E_OVERFLOW);
     b.ncount[i] = cnt;
     b.xr[i] = (float)xi;
     b.yr[i] = (float)yi;
@@ -624,25 +718,16 @@ __global__ __launch_bounds__(kBlock) void k_density(Params p, Buffers b, int32_t
   if (real) {
     const V4 pi = p4[i];
     const R rc2 = (R)p.rc2, a = (R)p.a, rc = (R)p.rc, rhoc = (R)p.rhoc, drhoc = (R)p.drhoc;
-    const int cnt = b.ncount[i];
-    const int my = (cnt > lane) ? (cnt - lane + LPA - 1) / LPA : 0;
+    // slots per lane: the list is padded with the far-away sentinel to whole
+    // passes, so every slot of a pass holds a valid index
+    const int npl = pass_slots<LPA>(b.ncount[i]);
     const int4 *nb4 = reinterpret_cast<const int4 *>(b.nbr) + (size_t)i * LPA + lane;
-    // two groups of four indices per pass: eight independent gathers in flight
-    for (int s = 0; s < my; s += 2 * kGroup) {
-      const int4 ja = nb4[(size_t)(s / kGroup) * p.nbr_stride];
-      const int4 jb = (s + kGroup < my) ? nb4[(size_t)(s / kGroup + 1) * p.nbr_stride] : make_int4(0, 0, 0, 0);
-      const int rem = my - s;
-      const int ii = (int)i;
-      const int jv[8] = {ja.x, rem > 1 ? ja.y : ii, rem > 2 ? ja.z : ii, rem > 3 ? ja.w : ii,
-                         rem > 4 ? jb.x : ii, rem > 5 ? jb.y : ii, rem > 6 ? jb.z : ii, rem > 7 ? jb.w : ii};
-      V4 pj[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) pj[u] = p4[jv[u]];
+    pair_passes(p4, nb4, p.nbr_stride, npl, [&](const V4(&pj)[8]) {
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const R dx = pj[u].x - pi.x, dy = pj[u].y - pi.y, dz = pj[u].z - pi.z;
         const R r2 = dx * dx + dy * dy + dz * dz;
-        if (u < rem && r2 < rc2) {
+        if (r2 < rc2) {
           const R rinv = rsqrt_r(r2);
           const R rr = r2 * rinv;
           if (NM == 2) {
@@ -655,7 +740,7 @@ __global__ __launch_bounds__(kBlock) void k_density(Params p, Buffers b, int32_t
           }
         }
       }
-    }
+    });
   }
 #pragma unroll
   for (int o = LPA / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
@@ -696,30 +781,21 @@ __global__ __launch_bounds__(kBlock) void k_force(Params p, Buffers b, int32_t k
   const bool real = g != kPad;
   const V4 *p4 = reinterpret_cast<const V4 *>(b.pos4);
   R fx = 0, fy = 0, fz = 0, ep = 0, w = 0;
-  int npair = 0;
   if (real) {
     const V4 pi = p4[i];
     const R rc2 = (R)p.rc2, a = (R)p.a, rc = (R)p.rc, eps = (R)p.eps;
     const R nn = (R)p.n, mm = (R)p.m;
     const R Vc = (R)p.Vc, dVc = (R)p.dVc, drhoc = (R)p.drhoc;
-    const int cnt = b.ncount[i];
-    const int my = (cnt > lane) ? (cnt - lane + LPA - 1) / LPA : 0;
+    // slots per lane: the list is padded with the far-away sentinel to whole
+    // passes, so every slot of a pass holds a valid index
+    const int npl = pass_slots<LPA>(b.ncount[i]);
     const int4 *nb4 = reinterpret_cast<const int4 *>(b.nbr) + (size_t)i * LPA + lane;
-    for (int s = 0; s < my; s += 2 * kGroup) {
-      const int4 ja = nb4[(size_t)(s / kGroup) * p.nbr_stride];
-      const int4 jb = (s + kGroup < my) ? nb4[(size_t)(s / kGroup + 1) * p.nbr_stride] : make_int4(0, 0, 0, 0);
-      const int rem = my - s;
-      const int ii = (int)i;
-      const int jv[8] = {ja.x, rem > 1 ? ja.y : ii, rem > 2 ? ja.z : ii, rem > 3 ? ja.w : ii,
-                         rem > 4 ? jb.x : ii, rem > 5 ? jb.y : ii, rem > 6 ? jb.z : ii, rem > 7 ? jb.w : ii};
-      V4 pj[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) pj[u] = p4[jv[u]];
+    pair_passes(p4, nb4, p.nbr_stride, npl, [&](const V4(&pj)[8]) {
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const R dx = pj[u].x - pi.x, dy = pj[u].y - pi.y, dz = pj[u].z - pi.z;
         const R r2 = dx * dx + dy * dy + dz * dz;
-        if (u < rem && r2 < rc2) {
+        if (r2 < rc2) {
           const R rinv = rsqrt_r(r2);
           const R rr = r2 * rinv;
           R Vs, gg;
@@ -750,10 +826,9 @@ __global__ __launch_bounds__(kBlock) void k_force(Params p, Buffers b, int32_t k
           fz += f * dz;
           ep += Vs;
           w += f * dz * dz;
-          ++npair;
         }
       }
-    }
+    });
   }
 #pragma unroll
   for (int o = LPA / 2; o > 0; o >>= 1) {
@@ -762,7 +837,6 @@ __global__ __launch_bounds__(kBlock) void k_force(Params p, Buffers b, int32_t k
     fz += __shfl_xor(fz, o);
     ep += __shfl_xor(ep, o);
     w += __shfl_xor(w, o);
-    npair += __shfl_xor(npair, o);
   }
   long long q[kNQ] = {0, 0, 0, 0, 0, 0, 0, 0};
   if (lane == 0 && real) {
@@ -789,7 +863,6 @@ __global__ __launch_bounds__(kBlock) void k_force(Params p, Buffers b, int32_t k
     q[Q_EPAIR] = to_fix(0.5 * (double)ep);
     q[Q_WZZ] = to_fix(-0.5 * (double)w);
     if (g == 2) q[Q_RZ] = to_fix(-Fz);
-    q[Q_PAIRS] = npair;
   }
   block_atoms_add<kNQ, kBlock / LPA>(q, lane == 0, threadIdx.x / LPA,
                                      slot_row(b, p.n_rep, par, r, blockIdx.x & (kSlots - 1)));
@@ -924,27 +997,53 @@ __global__ __launch_bounds__(1024) void k_scan_cells(Params p, Buffers b, int32_
   const int32_t *cnt = b.cell_count + rp.cell_off;
   int32_t *st = b.cell_start + rp.cell_off;
   int32_t *cur = cursor + rp.cell_off;
-  __shared__ int64_t part[1024];
+  // per-thread chunk sums, then an exclusive scan over the 1024 threads:
+  // inclusive scans within each wavefront (shuffles), then over the 16
+  // wavefront totals.  Counts stay below 2^27, so 32-bit sums suffice.
+  __shared__ int wsum[16];
   const int64_t per = (nc + 1023) / 1024;
   const int64_t lo = threadIdx.x * per, hi = min(nc, lo + per);
-  int64_t s = 0;
-  for (int64_t c = lo; c < hi; ++c) s += cnt[c];
-  part[threadIdx.x] = s;
+  int s = 0;
+  // chunks of 16 independent loads: a thread's cells cost a few load
+  // latencies, not one per cell
+  for (int64_t c0 = lo; c0 < hi; c0 += 16) {
+    int v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[u] = (c0 + u < hi) ? cnt[c0 + u] : 0;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) s += v[u];
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int v = s;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(v, o);
+    if (lane >= o) v += t;
+  }
+  if (lane == 63) wsum[wid] = v;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int64_t run = 0;
-    for (int t = 0; t < 1024; ++t) {
-      const int64_t v = part[t];
-      part[t] = run;
-      run += v;
+  if (wid == 0) {
+    int w = lane < 16 ? wsum[lane] : 0;
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) {
+      const int t = __shfl_up(w, o);
+      if (lane >= o) w += t;
     }
+    if (lane < 16) wsum[lane] = w;
   }
   __syncthreads();
-  int64_t run = rp.abeg + part[threadIdx.x];
-  for (int64_t c = lo; c < hi; ++c) {
-    st[c] = (int32_t)run;
-    cur[c] = (int32_t)run;
-    run += cnt[c];
+  int64_t run = rp.abeg + (v - s) + (wid > 0 ? wsum[wid - 1] : 0);
+  for (int64_t c0 = lo; c0 < hi; c0 += 16) {
+    int w[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) w[u] = (c0 + u < hi) ? cnt[c0 + u] : 0;
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      if (c0 + u < hi) {
+        st[c0 + u] = (int32_t)run;
+        cur[c0 + u] = (int32_t)run;
+        run += w[u];
+      }
   }
 }
 

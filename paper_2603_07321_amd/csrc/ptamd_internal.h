@@ -24,7 +24,6 @@ enum : int {
   Q_WZZ = 3,   // W_zz = -1/2 sum_i sum_j g_ij dz^2 / r (eV)
   Q_RZ = 4,    // -sum_{top} F^int_z (eV/A)
   Q_EMB = 5,   // sum_i B(rhobar_i) (eV)
-  Q_PAIRS = 6, // pairs within rc (directed), diagnostic
   Q_SPARE = 7
 };
 
@@ -156,6 +155,10 @@ struct Buffers {
 // four indices, and consecutive (atom, lane) pairs are adjacent, so the 64
 // lanes of a wave read 1 KiB contiguously.  stride = ntot * lpa.
 constexpr int kGroup = 4;
+// The pair kernels take 2 groups (8 slots) per lane and pass; every atom's
+// list is padded with the sentinel index ntot up to a whole number of
+// passes of all its lanes (8 * lanes entries), so the loops need no tail.
+constexpr int kPass = 2 * kGroup;
 __host__ __device__ inline size_t nbr_index(int64_t i, int e, int lpa, int64_t stride) {
   const int l = e % lpa, s = e / lpa;
   return ((size_t)(s / kGroup) * (size_t)stride + (size_t)i * lpa + l) * kGroup + (s % kGroup);

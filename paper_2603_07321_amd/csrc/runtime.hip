@@ -195,7 +195,8 @@ static void alloc_buffers(Buffers &b, int64_t ntot, int precision, bool primary)
   b.x = dalloc<double>(ntot); b.y = dalloc<double>(ntot); b.z = dalloc<double>(ntot);
   b.vx = dalloc<double>(ntot); b.vy = dalloc<double>(ntot); b.vz = dalloc<double>(ntot);
   b.fx = dalloc<double>(ntot); b.fy = dalloc<double>(ntot); b.fz = dalloc<double>(ntot);
-  b.pos4 = precision ? (void *)dalloc<float4>(ntot) : (void *)dalloc<double4>(ntot);
+  // one more entry: the list sentinel (index ntot), parked far away
+  b.pos4 = precision ? (void *)dalloc<float4>(ntot + 1) : (void *)dalloc<double4>(ntot + 1);
   b.group = dalloc<uint8_t>(ntot);
   b.orig = dalloc<int32_t>(ntot);
   b.cell = dalloc<int32_t>(ntot);
@@ -243,7 +244,7 @@ static void upload_reps(ptamd_system *s) {
 }
 
 static void alloc_list(ptamd_system *s, int cap) {
-  const int q = s->lpa * kGroup;
+  const int q = s->lpa * kPass;  // lists are padded to whole passes of every lane
   cap = (cap + q - 1) / q * q;
   dfree(s->B.nbr);
   s->B.nbr = nullptr;
@@ -346,7 +347,8 @@ static ptamd_system *create_from_hosts(const std::vector<HostState> &hs, const s
       s->nreal += n;
     }
     s->ntot = off;
-    if (s->ntot >= (int64_t)1 << 31) fail(PTAMD_EINVAL, "too many atoms for 32-bit indices");
+    // gathers address pos4 with 32-bit byte offsets: (ntot + 1) * 32 B < 4 GiB
+    if (s->ntot + 1 >= (int64_t)1 << 27) fail(PTAMD_EINVAL, "too many atoms (at most 2^27 - 2)");
     s->lpa = md.lanes_per_atom ? md.lanes_per_atom : auto_lpa(s->nreal);
 
     Params &P = s->P;
@@ -421,6 +423,18 @@ static ptamd_system *create_from_hosts(const std::vector<HostState> &hs, const s
     HIPCHK(hipMemsetAsync(B.fz, 0, 8 * N, s->stream));
     Control c0{};
     h2d(s, B.ctl, &c0, sizeof(Control));
+    {
+      // the sentinel that pads Verlet lists: r^2 ~ 3e36 against any atom, in
+      // FP32 too, so it never passes the cutoff test; B' = 0
+      const double far = 1.0e18;
+      if (s->precision) {
+        const float4 v = make_float4((float)far, (float)far, (float)far, 0.f);
+        h2d(s, reinterpret_cast<float4 *>(B.pos4) + N, &v, sizeof v);
+      } else {
+        const double4 v = make_double4(far, far, far, 0.0);
+        h2d(s, reinterpret_cast<double4 *>(B.pos4) + N, &v, sizeof v);
+      }
+    }
     upload_reps(s);
     s->need_sort = true;
     return s;
@@ -578,10 +592,44 @@ static void raise_err(int err) {
   if (err & E_STATE) fail(PTAMD_ESTATE, "thermostat met T <= 0 or lambda^2 < 0");
 }
 
+struct ChunkStats {
+  double drift = 0.0;  // max distance from the sorted position
+  double vmax = 0.0;   // max speed
+  double ldisp = 0.0;  // max distance from the position at the list build
+};
+
+// Maxima over all replicas of the last statistics pass (h_stat).
+static ChunkStats parse_stats(const ptamd_system *s) {
+  double d2 = 0.0, v2 = 0.0, l2 = 0.0;
+  for (int r = 0; r < s->n_rep; ++r)
+    for (int sl = 0; sl < kSlots; ++sl) {
+      const unsigned long long *row = &s->h_stat[((size_t)r * kSlots + sl) * kStat];
+      double a, b, c;
+      std::memcpy(&a, &row[0], 8);
+      std::memcpy(&b, &row[1], 8);
+      std::memcpy(&c, &row[8], 8);
+      d2 = std::max(d2, a);
+      v2 = std::max(v2, b);
+      l2 = std::max(l2, c);
+    }
+  ChunkStats cs;
+  cs.drift = std::sqrt(d2);
+  cs.vmax = std::sqrt(v2);
+  cs.ldisp = std::sqrt(l2);
+  return cs;
+}
+
+static ChunkStats chunk_stats(ptamd_system *s) {
+  read_stats(s);
+  return parse_stats(s);
+}
+
 // Forces at the current positions (burst start, force hook): a Verlet-list
 // build, the density pass and the force pass without the kick.
 static void initial_forces(ptamd_system *s) {
   s->msum_valid = false;
+  // the build below needs every atom within the margin of its sorted bin
+  if (!s->need_sort && s->stats_valid && parse_stats(s).drift > 0.8 * s->margin) s->need_sort = true;
   if (s->need_sort) sort_system(s);
   launch_burst_begin(s->P, s->B, s->n_rep, s->stream);
   launch_set_base(s->B, 0, s->stream);
@@ -607,32 +655,6 @@ static void initial_forces(ptamd_system *s) {
   raise_err(s->h_ctl->err);
 }
 
-struct ChunkStats {
-  double drift = 0.0;  // max distance from the sorted position
-  double vmax = 0.0;   // max speed
-  double ldisp = 0.0;  // max distance from the position at the list build
-};
-
-static ChunkStats chunk_stats(ptamd_system *s) {
-  read_stats(s);
-  double d2 = 0.0, v2 = 0.0, l2 = 0.0;
-  for (int r = 0; r < s->n_rep; ++r)
-    for (int sl = 0; sl < kSlots; ++sl) {
-      const unsigned long long *row = &s->h_stat[((size_t)r * kSlots + sl) * kStat];
-      double a, b, c;
-      std::memcpy(&a, &row[0], 8);
-      std::memcpy(&b, &row[1], 8);
-      std::memcpy(&c, &row[8], 8);
-      d2 = std::max(d2, a);
-      v2 = std::max(v2, b);
-      l2 = std::max(l2, c);
-    }
-  ChunkStats cs;
-  cs.drift = std::sqrt(d2);
-  cs.vmax = std::sqrt(v2);
-  cs.ldisp = std::sqrt(l2);
-  return cs;
-}
 
 // Burst of n_steps steps, or (conv != nullptr) of at most conv->n_max steps
 // that each replica ends at the first checkpoint where its running averages
@@ -682,21 +704,24 @@ static void run_burst(ptamd_system *s, int64_t n_steps, ptamd_averages *out, con
   int64_t step = 1;
   int chunk = kMaxChunk;  // the same schedule for every burst: results depend on the inputs only
   while (step <= n_steps) {
-    // Chunk length: no atom may move more than half the skin from its
-    // list-build position, nor more than 0.8 of the binning margin from its
-    // sorted position, within the chunk; the per-step bound is 1.5 x the
-    // largest speed times dt.  Sort and list build happen between chunks.
+    // Chunk length: no atom may move more than 0.45 skin from its list-build
+    // position within the chunk; the per-step bound is 1.5 x the largest
+    // speed times dt.  Sort and list build happen between chunks.  The bins
+    // only matter when a list is built (the build needs every atom within
+    // the binning margin of its sorted bin, and checks it), so the drift
+    // since the last sort is tested there: a build with drift beyond 0.8
+    // margin sorts first.
     const double vb = std::max(st.vmax, 1e-4) * s->md.dt_fs * 1.5;
-    if (st.drift > 0.5 * s->margin) s->need_sort = true;
-    if (s->need_sort) {
-      sort_system(s);
-      st.drift = 0.0;
-    }
     const double skin_room = 0.45 * s->skin;
     if (!s->need_build && st.ldisp + kMinChunk * vb > skin_room) s->need_build = true;
+    if (s->need_build && st.drift > 0.8 * s->margin) s->need_sort = true;
+    if (s->need_sort) {
+      sort_system(s);  // a new order: the lists are rebuilt
+      st.drift = 0.0;
+    }
     const bool build = s->need_build;
     if (build) st.ldisp = 0.0;
-    int K = (int)std::min<double>({(skin_room - st.ldisp) / vb, (0.8 * s->margin - st.drift) / vb, (double)chunk});
+    int K = (int)std::min<double>((skin_room - st.ldisp) / vb, (double)chunk);
     K = std::max(K, kMinChunk);
     K = (int)std::min<int64_t>(K, n_steps - step + 1);
     if (conv) {

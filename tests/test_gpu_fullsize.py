@@ -118,3 +118,23 @@ def test_autotune_restores_state():
     assert info["lanes_per_atom"] == choice["lanes_per_atom"]
     for k in st0:
         assert np.array_equal(st0[k], st1[k])
+
+
+def test_convergence_stop_with_more_blocks_than_resident():
+    """500,000 atoms: the kick launch has more blocks than the chip holds at
+    once, so blocks start after the first block has recorded the stopping
+    sample.  Every block must still take that step's lambda: the stopped
+    state equals a fixed burst of the same length (FP64, to rounding)."""
+    md = P.md_params(precision=0, lanes_per_atom=2)
+    with P.System.cube(50, T0=300.0, seed=1, md=md) as g:
+        avg, ns = g.run_until_converged(P.conv_params(10, 100, (1e9, 0, 0, 0)))
+        st = g.get_state()
+    with P.System.cube(50, T0=300.0, seed=1, md=md) as g:
+        ref = g.run_fast_md(20)[0]
+        st2 = g.get_state()
+    assert ns[0] == 20 and avg[0]["n_samples"] == 20
+    for k in ("vx", "vy", "vz"):
+        dv = np.abs(st[k] - st2[k]).max() / np.abs(st2[k]).max()
+        assert dv <= 1e-9, (k, dv)
+    assert np.abs(st["z"] - st2["z"]).max() <= 1e-9
+    assert avg[0]["ke"] == pytest.approx(ref["ke"], rel=1e-10)
