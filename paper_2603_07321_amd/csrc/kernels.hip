@@ -714,10 +714,14 @@ __global__ __launch_bounds__(kBlock) void k_density(Params p, Buffers b, int32_t
   const uint8_t g = b.group[i];
   const bool real = g != kPad;
   const V4 *p4 = reinterpret_cast<const V4 *>(b.pos4);
-  R acc = (R)0;
+  // Sutton-Chen: sum of (a/r)^m, of r and the pair count; the shift
+  // rho_s = (a/r)^m - rhoc - (r - rc) drhoc is applied once per atom.
+  // Tables: the sum of the interpolated rho.
+  R acc = (R)0, sr = (R)0;
+  int np = 0;
   if (real) {
     const V4 pi = p4[i];
-    const R rc2 = (R)p.rc2, a = (R)p.a, rc = (R)p.rc, rhoc = (R)p.rhoc, drhoc = (R)p.drhoc;
+    const R rc2 = (R)p.rc2, a = (R)p.a;
     // slots per lane: the list is padded with the far-away sentinel to whole
     // passes, so every slot of a pass holds a valid index
     const int npl = pass_slots<LPA>(b.ncount[i]);
@@ -729,24 +733,32 @@ __global__ __launch_bounds__(kBlock) void k_density(Params p, Buffers b, int32_t
         const R r2 = dx * dx + dy * dy + dz * dz;
         if (r2 < rc2) {
           const R rinv = rsqrt_r(r2);
-          const R rr = r2 * rinv;
           if (NM == 2) {
             R t;
-            const int kk = tab_interval<R>(p, rr, &t);
+            const int kk = tab_interval<R>(p, r2 * rinv, &t);
             const V4 c = reinterpret_cast<const V4 *>(b.tab_r)[2 * kk];
             acc += c.x + t * (c.y + t * (c.z + t * c.w));
           } else {
-            acc += rho_pow<R, NM>(a * rinv, p.m) - rhoc - (rr - rc) * drhoc;
+            acc += rho_pow<R, NM>(a * rinv, p.m);
+            sr += r2 * rinv;
+            ++np;
           }
         }
       }
     });
   }
 #pragma unroll
-  for (int o = LPA / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  for (int o = LPA / 2; o > 0; o >>= 1) {
+    acc += __shfl_xor(acc, o);
+    if (NM != 2) {
+      sr += __shfl_xor(sr, o);
+      np += __shfl_xor(np, o);
+    }
+  }
   long long q[1] = {0};
   if (lane == 0 && real) {
-    const double rb = (double)acc;
+    double rb = (double)acc;
+    if (NM != 2) rb += -(double)np * p.rhoc - p.drhoc * ((double)sr - (double)np * p.rc);
     double Bp = 0.0, B = 0.0;
     if (NM == 2) {
       tab_embed(p, b.tab_F, rb, &B, &Bp);
@@ -755,7 +767,8 @@ __global__ __launch_bounds__(kBlock) void k_density(Params p, Buffers b, int32_t
       B = -p.c_eps * sq;
       Bp = -0.5 * p.c_eps / sq;
     }
-    reinterpret_cast<R *>(b.pos4)[4 * i + 3] = (R)Bp;
+    // the force pass reads B' (tables) or -m B' (Sutton-Chen, one product less per pair)
+    reinterpret_cast<R *>(b.pos4)[4 * i + 3] = (R)(NM == 2 ? Bp : -(double)p.m * Bp);
     q[0] = to_fix(B);
   }
   block_atoms_add<1, kBlock / LPA>(q, lane == 0, threadIdx.x / LPA,
@@ -780,12 +793,17 @@ __global__ __launch_bounds__(kBlock) void k_force(Params p, Buffers b, int32_t k
   const uint8_t g = b.group[i];
   const bool real = g != kPad;
   const V4 *p4 = reinterpret_cast<const V4 *>(b.pos4);
-  R fx = 0, fy = 0, fz = 0, ep = 0, w = 0;
+  // Sutton-Chen, with w_j = -m B'_j from the density pass:
+  //   dU/dr = [-n eps (a/r)^n + (w_i + w_j) (a/r)^m] / r - (dVc - (w_i + w_j) drhoc / m)
+  // and the pair energy V - Vc - (r - rc) dVc summed as sum(-n V), sum(r)
+  // and the pair count, shifted once per atom.  Tables: B' as is.
+  R fx = 0, fy = 0, fz = 0, ep = 0, w = 0, sr = 0;
+  int np = 0;
   if (real) {
     const V4 pi = p4[i];
-    const R rc2 = (R)p.rc2, a = (R)p.a, rc = (R)p.rc, eps = (R)p.eps;
-    const R nn = (R)p.n, mm = (R)p.m;
-    const R Vc = (R)p.Vc, dVc = (R)p.dVc, drhoc = (R)p.drhoc;
+    const R rc2 = (R)p.rc2, a = (R)p.a;
+    const R neps = -(R)p.n * (R)p.eps;
+    const R dVc = (R)p.dVc, dm = (R)(p.drhoc / p.m);
     // slots per lane: the list is padded with the far-away sentinel to whole
     // passes, so every slot of a pass holds a valid index
     const int npl = pass_slots<LPA>(b.ncount[i]);
@@ -797,34 +815,35 @@ __global__ __launch_bounds__(kBlock) void k_force(Params p, Buffers b, int32_t k
         const R r2 = dx * dx + dy * dy + dz * dz;
         if (r2 < rc2) {
           const R rinv = rsqrt_r(r2);
-          const R rr = r2 * rinv;
-          R Vs, gg;
+          R f;
           if (NM == 2) {
             // setfl tables: V = (r phi)/r, V' = ((r phi)' - V)/r, rho' from its spline
             R t;
-            const int kk = tab_interval<R>(p, rr, &t);
+            const int kk = tab_interval<R>(p, r2 * rinv, &t);
             const V4 cr = reinterpret_cast<const V4 *>(b.tab_r)[2 * kk];
             const V4 cp = reinterpret_cast<const V4 *>(b.tab_r)[2 * kk + 1];
             const R idr = (R)p.tab_inv_dr;
             const R drho = (cr.y + t * ((R)2 * cr.z + (R)3 * t * cr.w)) * idr;
             const R rphi = cp.x + t * (cp.y + t * (cp.z + t * cp.w));
             const R drphi = (cp.y + t * ((R)2 * cp.z + (R)3 * t * cp.w)) * idr;
-            Vs = rphi * rinv;
-            gg = (drphi - Vs) * rinv + (pi.w + pj[u].w) * drho;
+            const R V = rphi * rinv;
+            f = ((drphi - V) * rinv + (pi.w + pj[u].w) * drho) * rinv;
+            ep += V;
           } else {
             R tn, tm;
             sc_powers<R, NM>(a * rinv, p.n, p.m, &tn, &tm);
-            const R V = eps * tn;
-            const R dV = -nn * V * rinv;
-            const R drho = -mm * tm * rinv;
-            Vs = V - Vc - (rr - rc) * dVc;
-            gg = (dV - dVc) + (pi.w + pj[u].w) * (drho - drhoc);
+            const R A = neps * tn;  // -n V
+            const R ws = pi.w + pj[u].w;
+            const R C = ws * tm + A;
+            const R D = dVc - ws * dm;
+            f = (C * rinv - D) * rinv;
+            ep += A;
+            sr += r2 * rinv;
+            ++np;
           }
-          const R f = gg * rinv;
           fx += f * dx;
           fy += f * dy;
           fz += f * dz;
-          ep += Vs;
           w += f * dz * dz;
         }
       }
@@ -837,6 +856,10 @@ __global__ __launch_bounds__(kBlock) void k_force(Params p, Buffers b, int32_t k
     fz += __shfl_xor(fz, o);
     ep += __shfl_xor(ep, o);
     w += __shfl_xor(w, o);
+    if (NM != 2) {
+      sr += __shfl_xor(sr, o);
+      np += __shfl_xor(np, o);
+    }
   }
   long long q[kNQ] = {0, 0, 0, 0, 0, 0, 0, 0};
   if (lane == 0 && real) {
@@ -860,7 +883,10 @@ __global__ __launch_bounds__(kBlock) void k_force(Params p, Buffers b, int32_t k
       q[Q_MV2] = to_fix(p.mvv2e_m * (vx * vx + vy * vy + vz * vz));
       q[Q_MVZ2] = to_fix(p.mvv2e_m * vz * vz);
     }
-    q[Q_EPAIR] = to_fix(0.5 * (double)ep);
+    // pair energy of the atom: tables sum V; Sutton-Chen sums -n V, r and the count
+    const double epair = (NM == 2) ? (double)ep
+                                   : -(double)ep / p.n - (double)np * p.Vc - p.dVc * ((double)sr - (double)np * p.rc);
+    q[Q_EPAIR] = to_fix(0.5 * epair);
     q[Q_WZZ] = to_fix(-0.5 * (double)w);
     if (g == 2) q[Q_RZ] = to_fix(-Fz);
   }
