@@ -52,9 +52,10 @@ def kernel_source_hash() -> str:
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def measured_traffic(workload: str, precision: int, lanes: int):
+def measured_traffic(workload: str, precision: int, lanes: int, skin: float):
     """HBM bytes per force-kernel launch from the committed counter runs, or
-    None when the kernel source or launch shape differs from the profiled one."""
+    None when the kernel source, launch shape or list skin differs from the
+    profiled one."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
@@ -64,21 +65,20 @@ def measured_traffic(workload: str, precision: int, lanes: int):
         return None
     if t.get("workload") != workload or t.get("precision") != precision or t.get("lanes_per_atom") != lanes:
         return None
+    if t.get("skin") != skin:
+        return None
     return t.get("bytes_per_launch")
 
 
-def run_workload(P, wl, precision, lanes, steps, warmup, burst, autotune, tune_steps, stream, timing=True):
+def run_workload(P, wl, precision, lanes, steps, warmup, burst, autotune, tune_steps, stream, timing=True, skin=1.0):
     sc = P.sc_params()
-    md = P.md_params(precision=precision, lanes_per_atom=lanes)
+    md = P.md_params(precision=precision, lanes_per_atom=lanes, skin=skin)
     descs = [P.lattice_desc(nc, T0, seed) for nc, T0, seed in zip(wl.n_cells, wl.T0, wl.seeds)]
     if len(descs) > 1:
         sysm = P.System.batch(descs, sc=sc, md=md)
     else:
         sysm = P.System.cube(wl.n_cells[0], T0=wl.T0[0], seed=wl.seeds[0], sc=sc, md=md)
     sysm.set_stream(stream)
-    tune = sysm.autotune(probe_steps=tune_steps) if autotune else None
-    if timing:
-        sysm.kernel_timing(reset=True)  # switches on the force-kernel timing
     strained = any(d != 0.0 for d in wl.d_eps)
 
     def load_step():
@@ -88,7 +88,11 @@ def run_workload(P, wl, precision, lanes, steps, warmup, burst, autotune, tune_s
 
     for _ in range(warmup):
         load_step()
-    sysm.kernel_timing(reset=True)
+    # tuned on the warmed-up state the timed load steps continue from (the
+    # autotuner restores that state exactly); not timed
+    tune = sysm.autotune(probe_steps=tune_steps) if autotune else None
+    if timing:
+        sysm.kernel_timing(reset=True)  # switches on the force-kernel timing
     info0 = sysm.info()
     import torch
     torch.cuda.synchronize()
@@ -115,8 +119,9 @@ def main() -> int:
     ap.add_argument("--burst", type=int, default=None, help="MD steps per burst (default: the workload's)")
     ap.add_argument("--precision", type=int, default=None, help="1 mixed, 0 FP64 (default: the workload's)")
     ap.add_argument("--lanes", type=int, default=0)
+    ap.add_argument("--skin", type=float, default=1.0, help="Verlet skin in A when the autotuner is off")
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--tune-steps", type=int, default=100)
+    ap.add_argument("--tune-steps", type=int, default=200)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 side measurement")
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -158,7 +163,7 @@ def main() -> int:
         del src, dst
 
     r = run_workload(P, wl, precision, args.lanes, steps, args.warmup, burst, not args.no_autotune,
-                     args.tune_steps, stream)
+                     args.tune_steps, stream, skin=args.skin)
     n_atoms = r["n_atoms"]
     value = n_atoms * burst * steps / r["elapsed"]
     lanes = r["info1"]["lanes_per_atom"]
@@ -172,7 +177,7 @@ def main() -> int:
         "peak": peak,
         "unit": "TFLOP/s",
         "frac": (achieved / peak) if achieved else None,
-        "traffic": measured_traffic(args.workload, precision, lanes),
+        "traffic": measured_traffic(args.workload, precision, lanes, r["info1"]["skin"]),
         "kernel_avg_ms": r["k_ms"],
         "kernel_avg_ms_source": "in-kernel device wall clock, first step of every chunk in the timed region",
         "kernel_event_avg_ms": r["k_ev_ms"],
