@@ -2,6 +2,7 @@
 // reader and host evaluation.  Host code only.
 #include "eam_table.h"
 
+#include <algorithm>
 #include <cctype>
 #include <cmath>
 #include <fstream>
@@ -61,7 +62,8 @@ void spline_coefficients(const double *y, int n, double h, std::vector<double> &
 
 void spline_eval(const double *coef, int n, double h, double x, double *f, double *df) {
   const double sx = x / h;
-  int k = (int)std::floor(sx);
+  const double fk = std::floor(sx);  // clamped before the conversion (NaN: below)
+  int k = fk >= 0.0 ? (int)std::min(fk, (double)n) : -1;
   double t = sx - (double)k, over = 0.0;
   if (k < 0) {
     k = 0;

@@ -140,7 +140,8 @@ __device__ __forceinline__ void pair_passes(const V4 *p4, const int4 *nb4, int64
 // knot inside the table.
 template <class R> __device__ __forceinline__ int tab_interval(const Params &p, R r, R *t) {
   const R sx = r * (R)p.tab_inv_dr;
-  const int k = min((int)sx, p.tab_kmax);
+  // r = 0 (coincident atoms) gives NaN here: index 0, the NaN propagates
+  const int k = sx > (R)0 ? min((int)sx, p.tab_kmax) : 0;
   *t = sx - (R)k;
   return k;
 }
@@ -149,7 +150,9 @@ template <class R> __device__ __forceinline__ int tab_interval(const Params &p, 
 // the last knot F continues linearly with its end slope.
 __device__ __forceinline__ void tab_embed(const Params &p, const double *cF, double rb, double *F, double *dF) {
   const double sx = rb * p.tab_inv_drho;
-  int k = (int)sx;
+  // below the first knot (a table with negative rho) or NaN: the first
+  // interval, extrapolated; far above: clamped before the conversion
+  int k = sx > 0.0 ? (int)fmin(sx, (double)p.tab_nrho) : 0;
   double t = sx - (double)k, over = 0.0;
   if (k > p.tab_nrho - 2) {
     k = p.tab_nrho - 2;

@@ -347,8 +347,7 @@ static ptamd_system *create_from_hosts(const std::vector<HostState> &hs, const s
       s->nreal += n;
     }
     s->ntot = off;
-    // gathers address pos4 with 32-bit byte offsets: (ntot + 1) * 32 B < 4 GiB
-    if (s->ntot + 1 >= (int64_t)1 << 27) fail(PTAMD_EINVAL, "too many atoms (at most 2^27 - 2)");
+    if (s->ntot + 1 >= (int64_t)1 << 27) fail(PTAMD_EINVAL, "too many atoms");  // checked earlier too
     s->lpa = md.lanes_per_atom ? md.lanes_per_atom : auto_lpa(s->nreal);
 
     Params &P = s->P;
@@ -703,6 +702,7 @@ static void run_burst(ptamd_system *s, int64_t n_steps, ptamd_averages *out, con
   ChunkStats st = chunk_stats(s);
   int64_t step = 1;
   int chunk = kMaxChunk;  // the same schedule for every burst: results depend on the inputs only
+  int retries = 0;        // roll-backs since the last completed chunk
   while (step <= n_steps) {
     // Chunk length: no atom may move more than 0.45 skin from its list-build
     // position within the chunk; the per-step bound is 1.5 x the largest
@@ -721,8 +721,14 @@ static void run_burst(ptamd_system *s, int64_t n_steps, ptamd_averages *out, con
     }
     const bool build = s->need_build;
     if (build) st.ldisp = 0.0;
-    int K = (int)std::min<double>((skin_room - st.ldisp) / vb, (double)chunk);
-    K = std::max(K, kMinChunk);
+    // steps the fastest atom can take within the skin budget; at least one
+    // (a list build precedes any chunk with less room than kMinChunk steps)
+    const double room = (skin_room - st.ldisp) / vb;
+    if (room < 1.0)
+      fail(PTAMD_EESCAPE, "an atom moves more than 0.45 of the skin in one step (speed " +
+                              std::to_string(st.vmax) + " A/fs)");
+    int K = (int)std::min<double>(room, (double)chunk);
+    K = std::max(K, 1);
     K = (int)std::min<int64_t>(K, n_steps - step + 1);
     if (conv) {
       // end the chunk with the launch that decides the next checkpoint c
@@ -759,11 +765,14 @@ static void run_burst(ptamd_system *s, int64_t n_steps, ptamd_averages *out, con
       clear_err(s);
       s->need_sort = true;
       s->rollbacks++;
-      chunk = std::max(kMinChunk, K / 2);
+      chunk = std::max(1, K / 2);
       st = chunk_stats(s);
-      if (s->rollbacks > 1000000) fail(PTAMD_EOVERFLOW, "too many roll-backs");
+      if (++retries > 64)
+        fail((err & E_SKIN) ? PTAMD_EESCAPE : PTAMD_EOVERFLOW,
+             "a chunk could not be completed in 64 roll-backs (atoms moving faster than the list bounds allow)");
       continue;
     }
+    retries = 0;
     raise_err(err);
     if (build) {
       s->list_builds++;
@@ -1294,6 +1303,17 @@ const char *ptamd_last_error(void) { return g_last_error.c_str(); }
 
 const char *ptamd_version(void) { return "ptamd 0.1 (gfx950)"; }
 
+// Gathers address the position copy with 32-bit byte offsets, which bounds
+// the padded atom count (each replica padded to whole tiles, plus the list
+// sentinel) to 2^27 - 1; checked before anything is built.
+static void check_atom_total(const std::vector<int64_t> &counts) {
+  int64_t tot = 1;
+  for (int64_t n : counts) {
+    tot += (n + kTile - 1) / kTile * kTile;
+    if (tot >= (int64_t)1 << 27) fail(PTAMD_EINVAL, "too many atoms: at most 2^27 - 1 in all, padded to 256 per replica");
+  }
+}
+
 static void validate_desc(const ptamd_lattice_desc *d) {
   if (!d) fail(PTAMD_EINVAL, "lattice desc is NULL");
   if (d->fix_slabs ? d->n_cells < 4 : d->n_cells < 1)
@@ -1316,10 +1336,15 @@ ptamd_status ptamd_create_batch(int32_t n_replicas, const ptamd_lattice_desc *de
     if (!descs) fail(PTAMD_EINVAL, "descs is NULL");
     validate_sc(sc);
     validate_md(md);
+    std::vector<int64_t> counts(n_replicas);
+    for (int r = 0; r < n_replicas; ++r) {
+      validate_desc(&descs[r]);
+      counts[r] = 4 * (int64_t)descs[r].n_cells * descs[r].n_cells * descs[r].n_cells;
+    }
+    check_atom_total(counts);
     std::vector<HostState> hs(n_replicas);
     std::vector<double> T0(n_replicas);
     for (int r = 0; r < n_replicas; ++r) {
-      validate_desc(&descs[r]);
       build_cube(descs[r].n_cells, descs[r].lattice_a, descs[r].fix_slabs != 0, descs[r].T0, descs[r].seed, hs[r]);
       T0[r] = descs[r].T0;
     }
@@ -1335,7 +1360,8 @@ ptamd_status ptamd_create_system_from_state(int64_t n, const double *x, const do
   return guard([&] {
     if (!out) fail(PTAMD_EINVAL, "out is NULL");
     *out = nullptr;
-    if (n < 2 || n > (int64_t)1 << 30) fail(PTAMD_EINVAL, "need 2 <= n <= 2^30");
+    if (n < 2) fail(PTAMD_EINVAL, "need n >= 2");
+    check_atom_total(std::vector<int64_t>{n});
     if (!x || !y || !z || !vx || !vy || !vz || !group) fail(PTAMD_EINVAL, "NULL array");
     if (!(volume0 > 0.0) || !(area0 >= 0.0) || !(T0 >= 0.0)) fail(PTAMD_EINVAL, "need volume0 > 0, area0 >= 0, T0 >= 0");
     validate_sc(sc);
@@ -1347,6 +1373,8 @@ ptamd_status ptamd_create_system_from_state(int64_t n, const double *x, const do
     h.group.assign(group, group + n);
     for (int64_t i = 0; i < n; ++i) {
       if (h.group[i] > 2) fail(PTAMD_EINVAL, "group values must be 0, 1 or 2");
+      if (!std::isfinite(x[i]) || !std::isfinite(y[i]) || !std::isfinite(z[i]))
+        fail(PTAMD_EINVAL, "non-finite input position");
       if (!std::isfinite(vx[i]) || !std::isfinite(vy[i]) || !std::isfinite(vz[i]))
         fail(PTAMD_EINVAL, "non-finite input velocity");
       if (h.group[i] != 0) h.vx[i] = h.vy[i] = h.vz[i] = 0.0;

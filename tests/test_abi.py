@@ -70,3 +70,34 @@ def test_null_handle_rejected():
     import paper_2603_07321_amd as P
     with pytest.raises(P.PtamdError):
         P.run_fast_md(0, 10) if False else P._check(P._lib.ptamd_run_fast_md(None, 10, None))
+
+
+def test_too_many_atoms_rejected_before_any_work():
+    """Gathers address positions with 32-bit byte offsets: more than 2^27 - 1
+    padded atoms in one system is an argument error, reported at once (no
+    lattice is built, no device is touched)."""
+    import time
+    import paper_2603_07321_amd as P
+    cases = [[P.lattice_desc(330)], [P.lattice_desc(260), P.lattice_desc(260, seed=2)]]
+    for descs in cases:
+        t0 = time.perf_counter()
+        with pytest.raises(P.PtamdError) as ei:
+            P.create_batch(descs, P.sc_params(), P.md_params())
+        assert ei.value.name == "PTAMD_EINVAL" and "too many atoms" in P.last_error()
+        assert time.perf_counter() - t0 < 1.0
+    # the same bound for a caller's state (checked before the arrays are read)
+    h = P._SYS()
+    st = P._lib.ptamd_create_system_from_state(1 << 27, None, None, None, None, None, None, None, 1.0, 0.0, 0.0,
+                                               P.C.byref(P.sc_params()), P.C.byref(P.md_params()), P.C.byref(h))
+    assert st == -1 and "too many atoms" in P.last_error() and not h.value
+
+
+@pytest.mark.parametrize("n", [0, 1])
+def test_state_with_fewer_than_two_atoms_rejected(n):
+    import numpy as np
+    import paper_2603_07321_amd as P
+    a = np.zeros(n)
+    with pytest.raises(P.PtamdError) as ei:
+        P.create_system_from_state(a, a, a, a, a, a, np.zeros(n, np.uint8), 1.0, 0.0, 0.0,
+                                   P.sc_params(), P.md_params())
+    assert ei.value.name == "PTAMD_EINVAL"

@@ -16,7 +16,9 @@ def test_library_spline_matches_oracle(orc):
     T = orc.TabPotential(F, rho, rphi, drho, dr, rc)
     rng = np.random.default_rng(4)
     r = rng.uniform(1.2, rc, 400)
-    q = np.concatenate([rng.uniform(0.0, (len(F) - 1) * drho, 300), [(len(F) - 1) * drho + 7.5]])
+    top = (len(F) - 1) * drho
+    # below the first knot (negative densities of some tables) and far past the last
+    q = np.concatenate([rng.uniform(0.0, top, 300), [top + 7.5, top * 1e6, 1e12, -0.3 * drho, -2.5 * drho]])
     f1, d1 = P.eam_table_eval(F, rho, rphi, drho, dr, rc, 1, r)
     f2, d2 = P.eam_table_eval(F, rho, rphi, drho, dr, rc, 2, r)
     fF, dF = P.eam_table_eval(F, rho, rphi, drho, dr, rc, 0, q)

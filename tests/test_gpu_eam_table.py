@@ -121,3 +121,38 @@ def test_tabulated_batch_runs_and_converges(tables):
         avg, ns = b.run_until_converged(P.conv_params(50, 1000, (0.01, 0.01, 0, 0)))
     for a in avg:
         assert np.isfinite(a["pe"]) and a["n_samples"] > 0
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_negative_densities_extend_the_first_interval(tables, precision):
+    """Nothing makes a table's densities positive: with rho of the opposite
+    sign (a tenth of Sutton-Chen's) every atom's density lies some 200 knot
+    intervals below the first knot of F (rhobar about -11), where both sides
+    extend the first spline interval.  F is quadratic, so both splines are
+    that quadratic up to rounding; the extension multiplies the rounding of
+    the cubic coefficient by (rhobar / drho)^3 ~ 1e7, which leaves F' within
+    ~1e-12 of the exact 0.01 + 2e-4 rhobar on both sides (checked on the
+    host: ten times farther out, at rhobar = -110, both sides' F' are off by
+    1e-10, which is why the test stays this close to the table)."""
+    O = _orc()
+    F0, rho, rphi, drho, dr, rc = tables
+    q = np.arange(len(F0)) * drho
+    tab = (0.01 * q + 1e-4 * q ** 2, -0.1 * rho, rphi, drho, dr, rc)
+    s = _state(5, 0.1, 300.0, 75)
+    T = O.TabPotential(*tab)
+    ref = O.forces(s["x"], s["y"], s["z"], T.sc, s["group"])
+    F = np.stack([ref["fx"], ref["fy"], ref["fz"]], 1)
+    md = P.md_params(precision=precision, lanes_per_atom=4)
+    with P.System.from_state(s, T0=300.0, md=md) as g:
+        g.set_eam_table(*tab)
+        f = g.compute_forces()
+        avg = g.run_fast_md(50)[0]
+    G = np.stack([f["fx"], f["fy"], f["fz"]], 1)
+    err = _ferr(G, F)
+    du = abs(f["U"][0] - ref["U"]) / len(G)
+    print(f"\nnegative densities, precision {precision}: force {err:.2e}, U/atom {du:.2e}")
+    if precision == 0:
+        assert err <= 1e-9 and du <= 1e-10
+    else:
+        assert err <= 2e-4 and du <= 1e-5
+    assert np.isfinite(avg["pe"]) and np.isfinite(avg["szz"])
