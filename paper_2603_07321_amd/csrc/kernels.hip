@@ -365,7 +365,8 @@ __device__ void write_averages(const Control &c, const RepInfo &rp, RepAcc &A) {
 }
 
 // ---------------------------------------------------------------------------
-// kick-drift (mode 0) / finalize (mode 1)
+// kick-drift (mode 0; mode 2: a list rebuild point follows, see below) /
+// finalize (mode 1)
 // ---------------------------------------------------------------------------
 template <class R>
 __global__ __launch_bounds__(kBlock) void k_kick_drift(Params p, Buffers b, int32_t k, int32_t mode) {
@@ -381,12 +382,12 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(Params p, Buffers b, int3
   double vx = b.vx[i], vy = b.vy[i], vz = b.vz[i];
   double x = 0, y = 0, z = 0, fx = 0, fy = 0, fz = 0;
   float xr = 0.f, yr = 0.f, zr = 0.f;
-  if (mode == 0) {
+  if (mode != 1) {
     fx = b.fx[i]; fy = b.fy[i]; fz = b.fz[i];
     x = b.x[i]; y = b.y[i]; z = b.z[i];
     xr = b.xr[i]; yr = b.yr[i]; zr = b.zr[i];
   }
-  const int64_t step = b.ctl->base + k;  // mode 0: step being computed; mode 1: n_steps + 1
+  const int64_t step = b.ctl->base + k;  // mode 0, 2: step being computed; mode 1: n_steps + 1
   // A replica whose running averages converged in an earlier launch stays
   // frozen (the whole block leaves together).  One that converges in this
   // launch (at sample step - 1, written by its first block while others may
@@ -502,7 +503,7 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(Params p, Buffers b, int3
     double *dst = reinterpret_cast<double *>(&b.acc[r]);
     for (int t = (int)threadIdx.x - 64; t < kAccWords; t += 64) dst[t] = src[t];
   }
-  const bool step_on = mode == 0 && !s_stop;
+  const bool step_on = mode != 1 && !s_stop;
   if (!mob) {  // fixed or padding atom: v = 0, never moves
     if (p.msum && step_on && grp != kPad) {
       b.msx[i] += x;
@@ -536,7 +537,13 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(Params p, Buffers b, int3
     const double cx = x - s_rep.center[0], cy = y - s_rep.center[1], cz = z - s_rep.center[2];
     if (!(cx * cx + cy * cy + cz * cz <= p.esc2)) set_err(b, isfinite(x + y + z) ? E_ESCAPE : E_NONFINITE);
     const double ex = x - (double)xr, ey = y - (double)yr, ez = z - (double)zr;
-    if (ex * ex + ey * ey + ez * ez > p.half_skin2) set_err(b, E_SKIN);
+    const double e2 = ex * ex + ey * ey + ez * ez;
+    if (e2 > p.half_skin2) set_err(b, E_SKIN);
+    // At a rebuild point the lists must last until the next one: rebuild now
+    // if this atom's displacement since the build, plus what its speed
+    // (with 50% headroom) adds over the steps in between, reaches the limit.
+    if (mode == 2 && sqrt(e2) + p.trig_v * sqrt(vx * vx + vy * vy + vz * vz) > p.trig_lim)
+      atomicOr(&b.ctl->rebuild, 1);
     if (p.msum) {  // Eq. (mean_pos): this step's positions are sample s's
       b.msx[i] += x;
       b.msy[i] += y;
@@ -688,9 +695,14 @@ __device__ void build_one(const Params &p, const Buffers &b, int64_t i, int lane
   }
 }
 
-// Grid-stride over atoms: KB lanes per atom.
+// Grid-stride over atoms: KB lanes per atom.  cond != 0: a rebuild point
+// inside a chunk, which builds only when a kick-drift asked for it.
 template <class R, int LPA>
-__global__ __launch_bounds__(kBlock) void k_build(Params p, Buffers b) {
+__global__ __launch_bounds__(kBlock) void k_build(Params p, Buffers b, int32_t cond) {
+  if (cond) {
+    if (b.ctl->rebuild == 0) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(reinterpret_cast<unsigned long long *>(&b.ctl->nbuild), 1ull);
+  }
   const int lane = (int)(threadIdx.x & (KB - 1));
   const int64_t per_pass = (int64_t)gridDim.x * (kBlock / KB);
   for (int64_t i = (int64_t)blockIdx.x * (kBlock / KB) + threadIdx.x / KB; i < p.ntot; i += per_pass)
@@ -713,6 +725,8 @@ __global__ __launch_bounds__(kBlock) void k_density(Params p, Buffers b, int32_t
     unsigned long long *zp = b.slots + (size_t)(par ^ 1) * nz;
     for (size_t t = (size_t)gt; t < nz; t += (size_t)gridDim.x * kBlock) zp[t] = 0ull;
   }
+  // every block of a conditional build has read the request: clear it
+  if (gt == 0 && b.ctl->rebuild != 0) atomicAnd(&b.ctl->rebuild, 0);
   if (p.conv && b.acc[r].conv_step != 0) return;  // converged replica: frozen
   const uint8_t g = b.group[i];
   const bool real = g != kPad;
@@ -918,11 +932,38 @@ __device__ __forceinline__ unsigned long long okey(double v) {
 // stat rows: [replica][slot][kStat] = drift^2, v^2 (max, double bits), min
 // x,y,z and max x,y,z (order-preserving keys), displacement^2 since the list
 // build (max, double bits)
-__global__ void k_stat_init(unsigned long long *stat, int64_t rows) {
+// Block 0 also folds the per-block time stamps of a timed force launch
+// (n_stamps start/end pairs) into Control::kt_first / kt_last.
+__global__ void k_stat_init(unsigned long long *stat, int64_t rows, const unsigned long long *stamps,
+                            int64_t n_stamps, Control *ctl) {
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < rows * kStat;
        t += (int64_t)gridDim.x * blockDim.x) {
     const int c = (int)(t % kStat);
     stat[t] = (c >= 2 && c < 5) ? ~0ull : 0ull;
+  }
+  if (blockIdx.x != 0 || n_stamps == 0) return;
+  unsigned long long t0 = ~0ull, t1 = 0ull;
+  for (int64_t q = threadIdx.x; q < n_stamps; q += blockDim.x) {
+    t0 = min(t0, stamps[2 * q]);
+    t1 = max(t1, stamps[2 * q + 1]);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    t0 = min(t0, (unsigned long long)shfl_xor_ll((long long)t0, o));
+    t1 = max(t1, (unsigned long long)shfl_xor_ll((long long)t1, o));
+  }
+  __shared__ unsigned long long sh[2][kBlock / 64];
+  if ((threadIdx.x & 63) == 0) {
+    sh[0][threadIdx.x >> 6] = t0;
+    sh[1][threadIdx.x >> 6] = t1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
+      t0 = min(t0, sh[0][w]);
+      t1 = max(t1, sh[1][w]);
+    }
+    ctl->kt_first = t0;
+    ctl->kt_last = t1;
   }
 }
 
@@ -1329,20 +1370,20 @@ static bool is_al76(const Params &p) { return p.n == 7 && p.m == 6; }
 static int pot_form(const Params &p) { return p.tab ? 2 : (is_al76(p) ? 1 : 0); }
 
 template <class R>
-static void build_lpa(const Params &p, const Buffers &b, int lpa, hipStream_t s) {
+static void build_lpa(const Params &p, const Buffers &b, int lpa, int32_t cond, hipStream_t s) {
   const unsigned g = (unsigned)std::min<int64_t>(p.ntot * KB / kBlock, 4096);
   switch (lpa) {
-    case 1: hipLaunchKernelGGL((k_build<R, 1>), dim3(g), dim3(kBlock), 0, s, p, b); break;
-    case 2: hipLaunchKernelGGL((k_build<R, 2>), dim3(g), dim3(kBlock), 0, s, p, b); break;
-    case 4: hipLaunchKernelGGL((k_build<R, 4>), dim3(g), dim3(kBlock), 0, s, p, b); break;
-    case 8: hipLaunchKernelGGL((k_build<R, 8>), dim3(g), dim3(kBlock), 0, s, p, b); break;
-    default: hipLaunchKernelGGL((k_build<R, 16>), dim3(g), dim3(kBlock), 0, s, p, b); break;
+    case 1: hipLaunchKernelGGL((k_build<R, 1>), dim3(g), dim3(kBlock), 0, s, p, b, cond); break;
+    case 2: hipLaunchKernelGGL((k_build<R, 2>), dim3(g), dim3(kBlock), 0, s, p, b, cond); break;
+    case 4: hipLaunchKernelGGL((k_build<R, 4>), dim3(g), dim3(kBlock), 0, s, p, b, cond); break;
+    case 8: hipLaunchKernelGGL((k_build<R, 8>), dim3(g), dim3(kBlock), 0, s, p, b, cond); break;
+    default: hipLaunchKernelGGL((k_build<R, 16>), dim3(g), dim3(kBlock), 0, s, p, b, cond); break;
   }
 }
 
-void launch_build(const Params &p, const Buffers &b, int precision, int lpa, hipStream_t s) {
-  if (precision) build_lpa<float>(p, b, lpa, s);
-  else build_lpa<double>(p, b, lpa, s);
+void launch_build(const Params &p, const Buffers &b, int precision, int lpa, hipStream_t s, int32_t cond) {
+  if (precision) build_lpa<float>(p, b, lpa, cond, s);
+  else build_lpa<double>(p, b, lpa, cond, s);
 }
 
 void launch_density(const Params &p, const Buffers &b, int precision, int lpa, int32_t k, hipStream_t s) {
@@ -1368,10 +1409,10 @@ void launch_force(const Params &p, const Buffers &b, int precision, int lpa, int
   }
 }
 
-void launch_chunk_stats(const Params &p, const Buffers &b, hipStream_t s) {
+void launch_chunk_stats(const Params &p, const Buffers &b, hipStream_t s, int64_t n_stamps) {
   const int64_t rows = (int64_t)p.n_rep * kSlots;
   hipLaunchKernelGGL(k_stat_init, dim3((unsigned)std::min<int64_t>((rows * kStat + kBlock - 1) / kBlock, 1024)),
-                     dim3(kBlock), 0, s, b.stat, rows);
+                     dim3(kBlock), 0, s, b.stat, rows, b.ktime, n_stamps, b.ctl);
   hipLaunchKernelGGL(k_chunk_stats, dim3(tiles(p)), dim3(kBlock), 0, s, p, b);
 }
 

@@ -34,13 +34,13 @@ enum : int {
   E_OVERFLOW = 4,  // Verlet list capacity exceeded
   E_DRIFT = 8,     // an atom drifted beyond the binning margin before a list build
   E_STATE = 16,    // thermostat: T <= 0 or lambda^2 < 0
-  E_SKIN = 32      // an atom moved more than half the skin since the list build
+  E_SKIN = 32      // an atom moved more than half the skin since the list build (a trigger was missed)
 };
 
 // Device-resident control block (one per system).
 struct Control {
   int64_t base;      // absolute step index of the first step in the current chunk
-  int32_t spare;
+  int32_t rebuild;   // set by a kick-drift that finds the lists too old; cleared by the next density pass
   int32_t err;       // error bits
   int64_t n_steps;   // steps of the current burst
   int64_t se_block;  // samples per standard-error block (n_steps / 20; lag / 10 when testing convergence)
@@ -49,6 +49,8 @@ struct Control {
   int64_t conv_lag;       // k: checks at samples 2k, 3k, ..., each against the average k samples earlier
   double conv_tol[4];     // tolerance per state function (K, U, sigma_zz, T_z); <= 0: not tested
   double conv_floor[4];   // lower bound of the error's denominator (0: the plain relative error)
+  int64_t nbuild;         // list builds triggered on the device (running count)
+  uint64_t kt_first, kt_last;  // earliest start and latest end stamp of the last timed force launch
 };
 
 constexpr int kStat = 16;  // u64 entries per statistics row
@@ -97,7 +99,9 @@ struct Params {
   float rlist2_lo, rlist2_hi;  // FP32 pre-filter band around rlist2 (0.1%)
   double cull2;        // (rc + skin + margin)^2: cells farther than this hold no list candidate
   double bin_h;        // binning cell edge: (rlist + 2 margin) / 2, searched with a 5^3 stencil
-  double half_skin2;   // (skin/2)^2: displacement that triggers a list rebuild
+  double half_skin2;   // (skin/2)^2: displacement beyond which the lists are invalid
+  double trig_v;       // rebuild trigger: |x - x_build| + trig_v |v| > trig_lim at a rebuild point
+  double trig_lim;
   double margin2;      // binning margin^2
   double esc2;         // squared escape radius around the replica centre
   // integrator
@@ -169,13 +173,13 @@ void launch_burst_begin(const Params &p, const Buffers &b, int n_rep, hipStream_
 void launch_hold_group(const Buffers &b, int64_t ntot, int g, hipStream_t s);
 void launch_kick_drift(const Params &p, const Buffers &b, int precision, int32_t k, int32_t mode, hipStream_t s);
 void launch_pos4(const Params &p, const Buffers &b, int precision, hipStream_t s);
-void launch_build(const Params &p, const Buffers &b, int precision, int lpa, hipStream_t s);
+void launch_build(const Params &p, const Buffers &b, int precision, int lpa, hipStream_t s, int32_t cond = 0);
 void launch_density(const Params &p, const Buffers &b, int precision, int lpa, int32_t k, hipStream_t s);
 void launch_force(const Params &p, const Buffers &b, int precision, int lpa, int32_t k, int32_t mode,
                   hipStream_t s);
 void launch_set_base(const Buffers &b, int64_t base, hipStream_t s);
 void launch_set_ncells(const Buffers &b, int64_t n, hipStream_t s);
-void launch_chunk_stats(const Params &p, const Buffers &b, hipStream_t s);
+void launch_chunk_stats(const Params &p, const Buffers &b, hipStream_t s, int64_t n_stamps = 0);
 void launch_snapshot(const Buffers &b, double *snap, unsigned long long *snap_slots, double *snap_acc, int restore,
                      int64_t ntot, int64_t nslots, int64_t nacc, hipStream_t s);
 void launch_copy_back(const Params &p, const Buffers &b, const Buffers &scratch, int precision, hipStream_t s);

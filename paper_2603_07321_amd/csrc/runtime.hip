@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -51,7 +52,9 @@ static void dfree(void *p) {
 
 constexpr int kMaxDims = 128;       // binning grid cells per axis (atoms beyond are clamped into edge cells)
 constexpr int kMaxChunk = 256;     // steps per captured graph
-constexpr int kMinChunk = 4;
+constexpr int kRebuildEvery = 4;   // steps between the device-side list rebuild points of a chunk
+constexpr int kMinSortChunk = 16;  // sort first when the drift bound leaves a shorter chunk
+constexpr size_t kCtlWords = (sizeof(Control) + 7) / 8;
 
 struct RepHost {
   int64_t abeg = 0, aend = 0, nreal = 0, nmob = 0, ntop = 0;
@@ -113,6 +116,7 @@ struct ptamd_system {
   int64_t t_count = 0;
   int chunk = 64;
   int64_t steps_total = 0, sorts = 0, rollbacks = 0, list_builds = 0;
+  int64_t nbuild_seen = 0;  // device-side builds already counted in list_builds
   int64_t series_rows = 0;
 };
 
@@ -210,7 +214,7 @@ static void alloc_buffers(Buffers &b, int64_t ntot, int precision, bool primary)
 static void free_buffers(Buffers &b) {
   void *ptrs[] = {b.x, b.y, b.z, b.vx, b.vy, b.vz, b.fx, b.fy, b.fz, b.pos4, b.group, b.orig, b.cell,
                   b.xs, b.ys, b.zs, b.xr, b.yr, b.zr, b.nbr, b.ncount, b.cell_start, b.cell_count,
-                  b.blk_rep, b.rep, b.acc, b.slots, b.stat, b.series, b.ctl, b.ktime, b.msx, b.msy, b.msz,
+                  b.blk_rep, b.rep, b.acc, b.slots, b.stat, b.series, b.ktime, b.msx, b.msy, b.msz,
                   b.tab_r, b.tab_F};
   for (void *p : ptrs) dfree(p);
   b = Buffers{};
@@ -268,6 +272,9 @@ static void set_list_geometry(ptamd_system *s) {
   // the reference positions of both checks are stored in FP32: keep 1e-3 A
   // of slack (coordinates up to the 1e4 A escape bound round by < 6e-4 A)
   P.half_skin2 = (0.5 * s->skin - 1e-3) * (0.5 * s->skin - 1e-3);
+  // a rebuild point triggers 0.01 A short of that limit (room for an atom
+  // that starts from rest and accelerates)
+  P.trig_lim = 0.5 * s->skin - 1e-3 - 0.01;
   P.margin2 = (s->margin - 1e-3) * (s->margin - 1e-3);
 }
 
@@ -301,7 +308,7 @@ static ptamd_system *create_from_hosts(const std::vector<HostState> &hs, const s
     s->sc = sc;
     s->md = md;
     s->skin = md.skin;
-    s->margin = 1.0;
+    s->margin = 2.0;
     HIPCHK(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
     HIPCHK(hipEventCreate(&s->ev0));
     HIPCHK(hipEventCreate(&s->ev1));
@@ -376,8 +383,10 @@ static ptamd_system *create_from_hosts(const std::vector<HostState> &hs, const s
     B.rep = dalloc<RepInfo>(s->n_rep);
     B.acc = dalloc<RepAcc>(s->n_rep);
     B.slots = dalloc<unsigned long long>((size_t)2 * s->n_rep * kSlots * kNQ);
-    B.stat = dalloc<unsigned long long>((size_t)s->n_rep * kSlots * kStat);
-    B.ctl = dalloc<Control>(1);
+    // the control block follows the statistics rows: one copy brings both back
+    const size_t nst = (size_t)s->n_rep * kSlots * kStat;
+    B.stat = dalloc<unsigned long long>(nst + kCtlWords);
+    B.ctl = reinterpret_cast<Control *>(B.stat + nst);
     B.ktime = dalloc<unsigned long long>((size_t)2 * (s->ntot * 16 / kBlock + 1));
     s->d_key = dalloc<int32_t>(s->ntot);
     s->d_tmp = dalloc<int32_t>(s->ntot);
@@ -385,8 +394,8 @@ static ptamd_system *create_from_hosts(const std::vector<HostState> &hs, const s
     s->snap = dalloc<double>((size_t)12 * s->ntot);  // x, v, F and the position sums
     s->snap_slots = dalloc<unsigned long long>((size_t)2 * s->n_rep * kSlots * kNQ);
     s->snap_acc = dalloc<RepAcc>(s->n_rep);
-    HIPCHK(hipHostMalloc((void **)&s->h_ctl, sizeof(Control), 0));
-    HIPCHK(hipHostMalloc((void **)&s->h_stat, sizeof(unsigned long long) * s->n_rep * kSlots * kStat, 0));
+    HIPCHK(hipHostMalloc((void **)&s->h_stat, sizeof(unsigned long long) * (nst + kCtlWords), 0));
+    s->h_ctl = reinterpret_cast<Control *>(s->h_stat + nst);
     HIPCHK(hipHostMalloc((void **)&s->h_rep, sizeof(RepInfo) * s->n_rep, 0));
 
     alloc_list(s, list_capacity_guess(s));
@@ -442,7 +451,6 @@ static ptamd_system *create_from_hosts(const std::vector<HostState> &hs, const s
     free_buffers(s->S);
     dfree(s->d_key); dfree(s->d_tmp); dfree(s->d_perm); dfree(s->d_cursor);
     dfree(s->snap); dfree(s->snap_slots); dfree(s->snap_acc);
-    if (s->h_ctl) (void)hipHostFree(s->h_ctl);
     if (s->h_stat) (void)hipHostFree(s->h_stat);
     if (s->h_rep) (void)hipHostFree(s->h_rep);
     if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
@@ -463,12 +471,12 @@ static double okey_decode(unsigned long long u) {
   return d;
 }
 
-static void read_stats(ptamd_system *s) {
+// n_stamps: time-stamp pairs of a timed force launch to fold into Control.
+static void read_stats(ptamd_system *s, int64_t n_stamps = 0) {
   const size_t nst = (size_t)s->n_rep * kSlots * kStat;
-  launch_chunk_stats(s->P, s->B, s->stream);
+  launch_chunk_stats(s->P, s->B, s->stream, n_stamps);
   check_launch();
-  HIPCHK(hipMemcpyAsync(s->h_stat, s->B.stat, nst * 8, hipMemcpyDeviceToHost, s->stream));
-  HIPCHK(hipMemcpyAsync(s->h_ctl, s->B.ctl, sizeof(Control), hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(hipMemcpyAsync(s->h_stat, s->B.stat, (nst + kCtlWords) * 8, hipMemcpyDeviceToHost, s->stream));
   sync(s);
   s->stats_valid = true;
 }
@@ -544,17 +552,25 @@ static void sort_system(ptamd_system *s) {
 // MD steps
 // ---------------------------------------------------------------------------
 // Graph of K whole steps; with_build puts a Verlet-list build in front.
-static GraphEntry &get_graph(ptamd_system *s, int K, bool with_build) {
+// Every m-th step is a rebuild point: its kick-drift checks whether the lists
+// last until the next point (P.trig_v covers m - 1 steps), and a conditional
+// build follows that runs only when some atom asked for it.  The lists stay
+// valid inside the graph without a return to the host.
+static GraphEntry &get_graph(ptamd_system *s, int K, bool with_build, int m) {
   // every launch-time flag captured in the graph is part of its key
-  const int key = 16 * K + (s->P.msum ? 8 : 0) + (s->P.top_free ? 4 : 0) + (s->P.conv ? 2 : 0) + (with_build ? 1 : 0);
+  const int key = 32 * K + (m > 1 ? 16 : 0) + (s->P.msum ? 8 : 0) + (s->P.top_free ? 4 : 0) + (s->P.conv ? 2 : 0) +
+                  (with_build ? 1 : 0);
   auto it = s->graphs.find(key);
   if (it != s->graphs.end()) return it->second;
   GraphEntry g;
   hipGraph_t graph;
+  s->P.trig_v = (m - 1) * 1.5 * s->md.dt_fs;
   HIPCHK(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
   if (with_build) launch_build(s->P, s->B, s->precision, s->lpa, s->cap_stream);
   for (int32_t k = 0; k < K; ++k) {
-    launch_kick_drift(s->P, s->B, s->precision, k, 0, s->cap_stream);
+    const bool point = k % m == m - 1;
+    launch_kick_drift(s->P, s->B, s->precision, k, point ? 2 : 0, s->cap_stream);
+    if (point) launch_build(s->P, s->B, s->precision, s->lpa, s->cap_stream, 1);
     launch_density(s->P, s->B, s->precision, s->lpa, k, s->cap_stream);
     launch_force(s->P, s->B, s->precision, s->lpa, k, 0, s->cap_stream);
   }
@@ -580,8 +596,9 @@ static void snapshot(ptamd_system *s, bool restore) {
 static void read_ctl(ptamd_system *s) { d2h(s, s->h_ctl, s->B.ctl, sizeof(Control)); }
 
 static void clear_err(ptamd_system *s) {
-  const int32_t z = 0;
-  HIPCHK(hipMemcpyAsync(&s->B.ctl->err, &z, 4, hipMemcpyHostToDevice, s->stream));
+  static_assert(offsetof(Control, err) == offsetof(Control, rebuild) + 4, "rebuild and err are adjacent");
+  const int32_t z[2] = {0, 0};  // the error bits and a pending rebuild request
+  HIPCHK(hipMemcpyAsync(&s->B.ctl->rebuild, z, 8, hipMemcpyHostToDevice, s->stream));
   sync(s);
 }
 
@@ -618,8 +635,8 @@ static ChunkStats parse_stats(const ptamd_system *s) {
   return cs;
 }
 
-static ChunkStats chunk_stats(ptamd_system *s) {
-  read_stats(s);
+static ChunkStats chunk_stats(ptamd_system *s, int64_t n_stamps = 0) {
+  read_stats(s, n_stamps);
   return parse_stats(s);
 }
 
@@ -704,32 +721,32 @@ static void run_burst(ptamd_system *s, int64_t n_steps, ptamd_averages *out, con
   int chunk = kMaxChunk;  // the same schedule for every burst: results depend on the inputs only
   int retries = 0;        // roll-backs since the last completed chunk
   while (step <= n_steps) {
-    // Chunk length: no atom may move more than 0.45 skin from its list-build
-    // position within the chunk; the per-step bound is 1.5 x the largest
-    // speed times dt.  Sort and list build happen between chunks.  The bins
-    // only matter when a list is built (the build needs every atom within
-    // the binning margin of its sorted bin, and checks it), so the drift
-    // since the last sort is tested there: a build with drift beyond 0.8
-    // margin sorts first.
+    // Inside a chunk the lists are rebuilt on the device (rebuild points
+    // every m steps, see get_graph).  Per step an atom moves at most
+    // vb = 1.5 x the largest speed x dt.  A list build needs every atom
+    // within the binning margin of its sorted bin (and checks it), so a
+    // chunk ends before the drift since the last sort can reach the margin;
+    // the host sorts between chunks when too little of it is left.  It also
+    // builds when the lists might not last until the chunk's first rebuild
+    // point.
     const double vb = std::max(st.vmax, 1e-4) * s->md.dt_fs * 1.5;
     const double skin_room = 0.45 * s->skin;
-    if (!s->need_build && st.ldisp + kMinChunk * vb > skin_room) s->need_build = true;
-    if (s->need_build && st.drift > 0.8 * s->margin) s->need_sort = true;
+    const double drift_room = 0.95 * s->margin;
+    if (vb > skin_room)
+      fail(PTAMD_EESCAPE, "an atom moves more than 0.45 of the skin in one step (speed " +
+                              std::to_string(st.vmax) + " A/fs)");
+    // fast atoms (hot systems): a rebuild point at every step
+    const int m = (kRebuildEvery + 1) * vb <= skin_room ? kRebuildEvery : 1;
+    if (!s->need_build && st.ldisp + (m + 1) * vb > skin_room) s->need_build = true;
+    if (st.drift + kMinSortChunk * vb > drift_room) s->need_sort = true;
     if (s->need_sort) {
       sort_system(s);  // a new order: the lists are rebuilt
       st.drift = 0.0;
     }
     const bool build = s->need_build;
     if (build) st.ldisp = 0.0;
-    // steps the fastest atom can take within the skin budget; at least one
-    // (a list build precedes any chunk with less room than kMinChunk steps)
-    const double room = (skin_room - st.ldisp) / vb;
-    if (room < 1.0)
-      fail(PTAMD_EESCAPE, "an atom moves more than 0.45 of the skin in one step (speed " +
-                              std::to_string(st.vmax) + " A/fs)");
-    int K = (int)std::min<double>(room, (double)chunk);
-    K = std::max(K, 1);
-    K = (int)std::min<int64_t>(K, n_steps - step + 1);
+    int K = (int)std::min<double>((drift_room - st.drift) / vb, (double)chunk);
+    K = (int)std::min<int64_t>(std::max(K, 1), n_steps - step + 1);
     if (conv) {
       // end the chunk with the launch that decides the next checkpoint c
       // (the kick-drift of step c + 1), so a finished burst stops promptly
@@ -754,8 +771,10 @@ static void run_burst(ptamd_system *s, int64_t n_steps, ptamd_averages *out, con
       if (K > 1) launch_set_base(s->B, step + 1, s->stream);
     }
     check_launch();
-    if (K > done) HIPCHK(hipGraphLaunch(get_graph(s, K - done, build && !timing).exec, s->stream));
-    st = chunk_stats(s);
+    if (K > done) HIPCHK(hipGraphLaunch(get_graph(s, K - done, build && !timing, m).exec, s->stream));
+    st = chunk_stats(s, timing ? s->ntot * s->lpa / kBlock : 0);
+    s->list_builds += s->h_ctl->nbuild - s->nbuild_seen;
+    s->nbuild_seen = s->h_ctl->nbuild;
     const int err = s->h_ctl->err;
     if (err & (E_DRIFT | E_OVERFLOW | E_SKIN)) {
       // a bound the lists rely on did not hold: re-run the chunk from its start
@@ -782,15 +801,8 @@ static void run_burst(ptamd_system *s, int64_t n_steps, ptamd_averages *out, con
       float ms = 0.f;
       HIPCHK(hipEventElapsedTime(&ms, s->ev0, s->ev1));
       s->t_ev_ms += ms;
-      const int64_t nb = s->ntot * s->lpa / kBlock;
-      std::vector<unsigned long long> kt((size_t)2 * nb);
-      d2h(s, kt.data(), s->B.ktime, 16 * (size_t)nb);
-      unsigned long long t0 = ~0ull, t1 = 0ull;
-      for (int64_t q = 0; q < nb; ++q) {
-        t0 = std::min(t0, kt[2 * q]);
-        t1 = std::max(t1, kt[2 * q + 1]);
-      }
-      s->t_sum_ms += (double)(t1 - t0) / s->wall_khz;
+      // the stamps were folded into the control block with the statistics
+      s->t_sum_ms += (double)(s->h_ctl->kt_last - s->h_ctl->kt_first) / s->wall_khz;
       s->t_count++;
     }
     step += K;
@@ -1262,7 +1274,6 @@ static void destroy(ptamd_system *s) {
   free_buffers(s->S);
   dfree(s->d_key); dfree(s->d_tmp); dfree(s->d_perm); dfree(s->d_cursor);
   dfree(s->snap); dfree(s->snap_slots); dfree(s->snap_acc);
-  if (s->h_ctl) (void)hipHostFree(s->h_ctl);
   if (s->h_stat) (void)hipHostFree(s->h_stat);
   if (s->h_rep) (void)hipHostFree(s->h_rep);
   if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
