@@ -121,7 +121,7 @@ def main() -> int:
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--skin", type=float, default=1.0, help="Verlet skin in A when the autotuner is off")
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--tune-steps", type=int, default=200)
+    ap.add_argument("--tune-steps", type=int, default=400)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 side measurement")
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
