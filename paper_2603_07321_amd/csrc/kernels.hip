@@ -538,12 +538,16 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(Params p, Buffers b, int3
     if (!(cx * cx + cy * cy + cz * cz <= p.esc2)) set_err(b, isfinite(x + y + z) ? E_ESCAPE : E_NONFINITE);
     const double ex = x - (double)xr, ey = y - (double)yr, ez = z - (double)zr;
     const double e2 = ex * ex + ey * ey + ez * ez;
-    if (e2 > p.half_skin2) set_err(b, E_SKIN);
-    // At a rebuild point the lists must last until the next one: rebuild now
-    // if this atom's displacement since the build, plus what its speed
-    // (with 50% headroom) adds over the steps in between, reaches the limit.
-    if (mode == 2 && sqrt(e2) + p.trig_v * sqrt(vx * vx + vy * vy + vz * vz) > p.trig_lim)
-      atomicOr(&b.ctl->rebuild, 1);
+    if (mode == 2) {
+      // A rebuild point: the lists must last until the next one.  Rebuild
+      // before this step's density pass if this atom's displacement since
+      // the build, plus what its speed (with 50% headroom) adds over the
+      // steps in between, reaches the limit (which also covers an atom
+      // already past half the skin).
+      if (sqrt(e2) + p.trig_v * sqrt(vx * vx + vy * vy + vz * vz) > p.trig_lim) atomicOr(&b.ctl->rebuild, 1);
+    } else if (e2 > p.half_skin2) {
+      set_err(b, E_SKIN);  // the lists this step will use are no longer valid
+    }
     if (p.msum) {  // Eq. (mean_pos): this step's positions are sample s's
       b.msx[i] += x;
       b.msy[i] += y;
