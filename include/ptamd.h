@@ -370,12 +370,14 @@ ptamd_status ptamd_kernel_timing(ptamd_system *sys, double *avg_ms, double *avg_
                                  int32_t reset);
 /* Autotuner: times probe bursts of probe_steps (>= 10) steps from the
  * current state for lanes per atom in {2, 4, 8, 16} and Verlet skin in
- * {0.6, 1.0, 1.5} A, twice each (a candidate counts with its faster
+ * {0.6, 0.8, 1.0, 1.5} A, twice each (a candidate counts with its faster
  * probe), keeps the fastest (of the candidates within 3% of it, the one
  * with the largest skin: lists live shorter as a sample heats or
- * evaporates, which a probe from the current state does not see), and
+ * evaporates, which a probe from the current state does not see),
  * restores the state exactly
- * (positions, velocities, atom order).  With use_cache != 0 an earlier
+ * (positions, velocities, atom order), and builds the HIP graphs that
+ * bursts in the chosen configuration launch (with the force-kernel timing
+ * as set by ptamd_kernel_timing).  With use_cache != 0 an earlier
  * choice for the same atom count, replica count, precision and cutoff in
  * this process is reused without probing.  The choice changes summation
  * order (hence rounding), never the computed quantities.  Outputs may be

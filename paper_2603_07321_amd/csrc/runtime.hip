@@ -582,6 +582,24 @@ static GraphEntry &get_graph(ptamd_system *s, int K, bool with_build, int m) {
   return s->graphs[key] = g;
 }
 
+// Graph length of a chunk of K steps (the first of which is launched
+// directly when the force kernel is timed): 1..15, then multiples of 8, so
+// that the drift-bounded chunk lengths, which vary from chunk to chunk, need
+// at most 46 graphs (each new one costs a capture and an instantiation).
+static int chunk_graph_steps(int K, bool timing) {
+  const int g = K - (timing ? 1 : 0);
+  return g >= 16 ? g - g % 8 : g;
+}
+
+// Instantiates every chunk graph a fixed-length burst can launch with the
+// current launch configuration and flags (normal rebuild-point spacing).
+static void prepare_graphs(ptamd_system *s) {
+  for (int g = 1; g <= kMaxChunk; g += (g < 16 ? 1 : 8)) {
+    get_graph(s, g, false, kRebuildEvery);
+    if (!s->timing) get_graph(s, g, true, kRebuildEvery);
+  }
+}
+
 // Copy of the dynamic state (positions, velocities, forces, the reduction
 // slots and the burst accumulators) taken before each chunk, so that a chunk
 // can be re-run when a bound it relies on fails.  One kernel either way.
@@ -753,10 +771,7 @@ static void run_burst(ptamd_system *s, int64_t n_steps, ptamd_averages *out, con
       const int64_t c = std::max<int64_t>(2 * lag, (step - 1 + lag - 1) / lag * lag);
       if (c + 1 >= step) K = (int)std::min<int64_t>(K, c + 1 - step + 1);
     }
-    // graph lengths 1..15, then multiples of 8: the drift-bounded chunk
-    // lengths vary from chunk to chunk, and each new length would cost a
-    // graph instantiation (~0.3 ms); at most 46 lengths are ever built
-    if (K - (timing ? 1 : 0) >= 16) K -= (K - (timing ? 1 : 0)) % 8;
+    K = chunk_graph_steps(K, timing) + (timing ? 1 : 0);
     snapshot(s, false);
     launch_set_base(s->B, step, s->stream);
     int done = 0;
@@ -1193,6 +1208,7 @@ static void autotune(ptamd_system *s, int64_t probe_steps, int use_cache, int *o
     auto it = g_tune_cache.find(key);
     if (it != g_tune_cache.end()) {
       reconfigure(s, it->second.lpa, it->second.skin);
+      prepare_graphs(s);
       *out_lpa = it->second.lpa;
       *out_skin = it->second.skin;
       *out_ms = 0.0;
@@ -1200,6 +1216,13 @@ static void autotune(ptamd_system *s, int64_t probe_steps, int use_cache, int *o
     }
   }
   const int64_t N = s->ntot;
+  // probes run without the force-kernel timing (restored on the way out)
+  struct TimingOff {
+    ptamd_system *s;
+    bool was;
+    explicit TimingOff(ptamd_system *q) : s(q), was(q->timing) { q->timing = false; }
+    ~TimingOff() { s->timing = was; }
+  } timing_off(s);
   // save the state (in the current sorted order, with the order itself)
   double *save = dalloc<double>((size_t)6 * N);
   int32_t *save_o = dalloc<int32_t>(N);
@@ -1215,16 +1238,16 @@ static void autotune(ptamd_system *s, int64_t probe_steps, int use_cache, int *o
     d2d(s, save_g, s->B.group, N);
     sync(s);
     const int lpas[4] = {2, 4, 8, 16};
-    const double skins[3] = {0.6, 1.0, 1.5};
+    const double skins[4] = {0.6, 0.8, 1.0, 1.5};
     std::vector<ptamd_averages> tmp(s->n_rep);
     // two rounds over all candidates, each candidate timed by its faster
     // round: a single probe is noisy enough to flip close choices
-    double tbest[4][3];
+    double tbest[4][4];
     for (auto &row : tbest)
       for (double &t : row) t = 1e300;
     for (int round = 0; round < 2; ++round)
     for (int li = 0; li < 4; ++li)
-      for (int si = 0; si < 3; ++si) {
+      for (int si = 0; si < 4; ++si) {
         reconfigure(s, lpas[li], skins[si]);
         // warm-up with the probe's own length: from the same state the probe
         // follows the same chunk schedule, so every graph it launches is
@@ -1259,7 +1282,7 @@ static void autotune(ptamd_system *s, int64_t probe_steps, int use_cache, int *o
     // current state only, and the lists' lifetime shortens as a sample heats
     // or evaporates (the 62,500-atom cube at 300 K: skin 0.6 A probed ~1%
     // faster than 1.0 A, but ran its twenty load steps 2.6% slower).
-    for (int si = 2; si >= 0 && best_t > 1e299; --si)
+    for (int si = 3; si >= 0 && best_t > 1e299; --si)
       for (int li = 0; li < 4; ++li)
         if (tbest[li][si] <= 1.03 * t_min && tbest[li][si] < best_t) {
           best_t = tbest[li][si];
@@ -1273,6 +1296,10 @@ static void autotune(ptamd_system *s, int64_t probe_steps, int use_cache, int *o
   }
   dfree(save); dfree(save_o); dfree(save_g);
   reconfigure(s, best_l, best_s);
+  // every chunk graph the next bursts can launch, built now (with the
+  // caller's timing setting) rather than inside them
+  s->timing = timing_off.was;
+  prepare_graphs(s);
   g_tune_cache[key] = TuneChoice{best_l, best_s};
   *out_lpa = best_l;
   *out_skin = best_s;
