@@ -68,10 +68,14 @@ def _tolerances(errs, tested):
 
 
 # the third case tests T_z with an absolute floor on the error's denominator:
-# its running average passes through zero in these short runs
-@pytest.mark.parametrize("lag,n_max,tested,seed,floor", [(20, 300, (0, 1), 31, 0.0), (25, 250, (0,), 32, 0.0),
-                                                         (10, 150, (0, 3), 35, 1.0)])
-def test_run_until_converged_matches_oracle(lag, n_max, tested, seed, floor):
+# its running average passes through zero in these short runs; the fourth
+# uses a 0.3 A skin, so that the device-side list rebuilds fire often while
+# the convergence test runs
+@pytest.mark.parametrize("lag,n_max,tested,seed,floor,skin", [(20, 300, (0, 1), 31, 0.0, 1.0),
+                                                              (25, 250, (0,), 32, 0.0, 1.0),
+                                                              (10, 150, (0, 3), 35, 1.0, 1.0),
+                                                              (20, 300, (0, 1), 31, 0.0, 0.3)])
+def test_run_until_converged_matches_oracle(lag, n_max, tested, seed, floor, skin):
     O = _orc()
     s = _state(5, 0.05, 300.0, seed)
     fl = (0.0, 0.0, 0.0, floor)
@@ -84,7 +88,7 @@ def test_run_until_converged_matches_oracle(lag, n_max, tested, seed, floor):
     conv = P.conv_params(lag, n_max, tuple(tol), fl)
     os_ = _orc_state(s)
     R, ns_o, rser = T.run_until_converged(os_, O.sc_params(), O.md_params(), lag, n_max, tuple(tol), fl)
-    md = P.md_params(precision=0, lanes_per_atom=4)
+    md = P.md_params(precision=0, lanes_per_atom=4, skin=skin)
     with P.System.from_state(s, T0=300.0, md=md) as g:
         avg, ns = g.run_until_converged(conv)
         st = g.get_state()
