@@ -598,17 +598,6 @@ __device__ __forceinline__ double box_dist(double v, double o, double h, int n, 
   return fmax(fmax(lo - v, v - hi), 0.0);
 }
 
-// Decided in FP64 with the plain formula (no contraction): the same rounding
-// as the oracle.  An FP32 copy settles candidates away from the boundary.
-__device__ __forceinline__ bool in_list(const Params &p, const Buffers &b, int j, float4 q, float4 pi, double xi,
-                                        double yi, double zi) {
-  const float dx = q.x - pi.x, dy = q.y - pi.y, dz = q.z - pi.z;
-  const float d2 = dx * dx + dy * dy + dz * dz;
-  if (d2 < p.rlist2_lo) return true;
-  if (d2 > p.rlist2_hi) return false;
-  return dist2_plain(sub_plain(b.x[j], xi), sub_plain(b.y[j], yi), sub_plain(b.z[j], zi)) < p.rlist2;
-}
-
 template <class R> __device__ __forceinline__ float4 to_f4(typename V4T<R>::T v) {
   return make_float4((float)v.x, (float)v.y, (float)v.z, 0.f);
 }
@@ -656,11 +645,19 @@ __device__ void build_one(const Params &p, const Buffers &b, int64_t i, int lane
     rs[h2] = b.cell_start[row + lo];
     re[h2] = b.cell_start[row + hi] + b.cell_count[row + hi];
   }
-  // phase 2: scan the rows in order, KB x KCH candidates per pass
+  // phase 2: scan the rows in order, KB x KCH candidates per pass.  All
+  // KCH positions are loaded before any is tested, and every lane tests its
+  // candidates with the same FP32 arithmetic (no branch the compiler could
+  // sink a load into: a load issued inside one would wait for all four);
+  // only candidates in the band around rlist^2 take the FP64 decision.
   const int gbase = (threadIdx.x & 63) & ~(KB - 1);
   const unsigned long long gmask = (1ull << KB) - 1ull;
   const unsigned long long below = (1ull << lane) - 1ull;
   const int cap = p.cap_slots * LPA;
+  const int self = (int)i;
+  // list slot of entry e (the layout of nbr_index, in unsigned arithmetic)
+  const size_t slot_base = (size_t)self * (LPA * kGroup);
+  const size_t group_stride = (size_t)p.nbr_stride * kGroup;
   int cnt = 0;
   for (int q = 0; q < 25; ++q) {
     const int src = gbase + (q % KB);
@@ -677,10 +674,19 @@ __device__ void build_one(const Params &p, const Buffers &b, int64_t i, int lane
 #pragma unroll
       for (int u = 0; u < KCH; ++u) {
         const int j = jc[u];
-        const bool ok = j < e0 && (int64_t)j != i && in_list(p, b, j, qv[u], pi, xi, yi, zi);
+        const float dx = qv[u].x - pi.x, dy = qv[u].y - pi.y, dz = qv[u].z - pi.z;
+        const float d2 = dx * dx + dy * dy + dz * dz;
+        bool ok = (j < e0) & (j != self) & (d2 <= p.rlist2_hi);
+        // near rlist the FP64 plain formula (no contraction) decides, with the
+        // oracle's rounding; the FP32 copy settles candidates away from it
+        if (ok && !(d2 < p.rlist2_lo))
+          ok = dist2_plain(sub_plain(b.x[j], xi), sub_plain(b.y[j], yi), sub_plain(b.z[j], zi)) < p.rlist2;
         const unsigned long long m = (__ballot(ok) >> gbase) & gmask;
-        const int pos = cnt + __popcll(m & below);
-        if (ok && pos < cap) b.nbr[nbr_index(i, pos, LPA, p.nbr_stride)] = j;
+        const unsigned pos = (unsigned)cnt + (unsigned)__popcll(m & below);
+        if (ok && pos < (unsigned)cap) {
+          const unsigned l = pos % LPA, sl = pos / LPA;
+          b.nbr[(size_t)(sl / kGroup) * group_stride + slot_base + l * kGroup + sl % kGroup] = j;
+        }
         cnt += __popcll(m);
       }
     }
