@@ -365,48 +365,28 @@ __device__ void write_averages(const Control &c, const RepInfo &rp, RepAcc &A) {
 }
 
 // ---------------------------------------------------------------------------
-// kick-drift (mode 0; mode 2: a list rebuild point follows, see below) /
-// finalize (mode 1)
+// start of a step, replica-wide: lambda of the previous step, the sample it
+// completes and the convergence decision (shared by the kick-drift and the
+// density pass that takes the kick-drift over in the mixed form)
 // ---------------------------------------------------------------------------
-template <class R>
-__global__ __launch_bounds__(kBlock) void k_kick_drift(Params p, Buffers b, int32_t k, int32_t mode) {
-  using V4 = typename V4T<R>::T;
-  const int64_t tile = blockIdx.x;
-  const int r = (p.n_rep == 1) ? 0 : b.blk_rep[tile];
-  const int64_t i = tile * kTile + threadIdx.x;
-  // per-atom loads first: they stay in flight while wave 0 reduces lambda
-  // every array covers the padded range, so these loads need not wait for the group
-  const uint8_t grp = b.group[i];
-  const bool mob = moves_z(p, grp);
-  const bool zonly = grp != 0;  // a moving atom of the top region: along z only
-  double vx = b.vx[i], vy = b.vy[i], vz = b.vz[i];
-  double x = 0, y = 0, z = 0, fx = 0, fy = 0, fz = 0;
-  float xr = 0.f, yr = 0.f, zr = 0.f;
-  if (mode != 1) {
-    fx = b.fx[i]; fy = b.fy[i]; fz = b.fz[i];
-    x = b.x[i]; y = b.y[i]; z = b.z[i];
-    xr = b.xr[i]; yr = b.yr[i]; zr = b.zr[i];
-  }
-  const int64_t step = b.ctl->base + k;  // mode 0, 2: step being computed; mode 1: n_steps + 1
-  // A replica whose running averages converged in an earlier launch stays
-  // frozen (the whole block leaves together).  One that converges in this
-  // launch (at sample step - 1, written by its first block while others may
-  // still be starting) still takes this launch's lambda.
-  if (p.conv) {
-    const int64_t cs = b.acc[r].conv_step;
-    if (cs != 0 && cs < step - 1) return;
-  }
+struct StepStart {
+  double lam;          // thermostat factor of the previous step (1 at step 1)
+  int stop;            // the replica's averages converged at this step's sample
+  const RepInfo *rep;  // the replica's data, staged in LDS
+};
+
+// Needs all kBlock threads of the block (two barriers).  While the first
+// wavefront reduces the slots, the second stages in LDS what thread 0 needs
+// afterwards: the replica's data, the control block and, in the replica's
+// first block (which records the sample), the accumulators.  Thread 0 then
+// works from LDS instead of a chain of dependent global loads; the
+// accumulators go back at the end.  mode 1: finalize (the averages).
+__device__ StepStart step_start(const Params &p, const Buffers &b, int r, int64_t step, bool first, int32_t mode) {
   __shared__ double s_lam;
   __shared__ int s_stop;
-  // While the first wavefront reduces the slots, the second stages in LDS
-  // what thread 0 needs afterwards: the replica's data, the control block
-  // and, in the replica's first block (which records the sample), the
-  // accumulators.  Thread 0 then works from LDS instead of a chain of
-  // dependent global loads; the accumulators go back at the end.
   __shared__ RepAcc s_acc;
   __shared__ RepInfo s_rep;
   __shared__ Control s_ctl;
-  const bool first = p.n_rep == 1 ? tile == 0 : (tile == 0 || b.blk_rep[tile - 1] != r);
   constexpr int kAccWords = (int)(sizeof(RepAcc) / sizeof(double));
   constexpr int kRepWords = (int)(sizeof(RepInfo) / sizeof(double));
   constexpr int kCtlWords = (int)(sizeof(Control) / sizeof(double));
@@ -455,47 +435,45 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(Params p, Buffers b, int3
         for (int o = 32; o > 0; o >>= 1) q[t] += shfl_xor_ll(q[t], o);
   }
   __syncthreads();  // the staged copies are in LDS
-  {
-    if (threadIdx.x == 0) {
-      double lam = 1.0;
-      int stop = 0;
-      if (step > 1) {
-        double qd[6];
-        for (int t = 0; t < 6; ++t) qd[t] = (double)q[t] / kFix;
-        const RepInfo &rp = s_rep;
-        if (p.thermostat) {
-          const double T = qd[Q_MV2] / (rp.dof * p.kb);
-          const double l2 = 1.0 + (p.dt / p.tau) * (rp.T0 / T - 1.0);
-          if (!(T > 0.0) || !(l2 >= 0.0)) {
-            if (first) set_err(b, E_STATE);
-          } else {
-            lam = sqrt(l2);
-          }
-        }
-        const int64_t smp = step - 1;  // the sample this launch completes
-        const int64_t lag = p.conv ? s_ctl.conv_lag : 0;
-        const bool check = lag > 0 && smp % lag == 0;
-        if (check && smp >= 2 * lag) {
-          // every block of the replica takes the same decision from the same data
-          double m[5];
-          sample_values(p, rp, qd, lam, m);
-          stop = averages_converged(b, r, smp, lag, m) ? 1 : 0;
-        }
-        if (first) {
-          RepAcc &A = s_acc;
-          record_sample(p, b, s_ctl, rp, A, r, smp, qd, lam);
-          if (check) {
-            const double *S = A.sum[smp & 1];
-            double *C = A.csum[(smp / lag) & 1];
-            for (int f = 0; f < 4; ++f) C[f] = S[sum_col(f)];
-          }
-          if (stop) A.conv_step = smp;
-          if (stop || mode == 1) write_averages(s_ctl, rp, A);
+  if (threadIdx.x == 0) {
+    double lam = 1.0;
+    int stop = 0;
+    if (step > 1) {
+      double qd[6];
+      for (int t = 0; t < 6; ++t) qd[t] = (double)q[t] / kFix;
+      const RepInfo &rp = s_rep;
+      if (p.thermostat) {
+        const double T = qd[Q_MV2] / (rp.dof * p.kb);
+        const double l2 = 1.0 + (p.dt / p.tau) * (rp.T0 / T - 1.0);
+        if (!(T > 0.0) || !(l2 >= 0.0)) {
+          if (first) set_err(b, E_STATE);
+        } else {
+          lam = sqrt(l2);
         }
       }
-      s_lam = lam;
-      s_stop = stop;
+      const int64_t smp = step - 1;  // the sample this launch completes
+      const int64_t lag = p.conv ? s_ctl.conv_lag : 0;
+      const bool check = lag > 0 && smp % lag == 0;
+      if (check && smp >= 2 * lag) {
+        // every block of the replica takes the same decision from the same data
+        double m[5];
+        sample_values(p, rp, qd, lam, m);
+        stop = averages_converged(b, r, smp, lag, m) ? 1 : 0;
+      }
+      if (first) {
+        RepAcc &A = s_acc;
+        record_sample(p, b, s_ctl, rp, A, r, smp, qd, lam);
+        if (check) {
+          const double *S = A.sum[smp & 1];
+          double *C = A.csum[(smp / lag) & 1];
+          for (int f = 0; f < 4; ++f) C[f] = S[sum_col(f)];
+        }
+        if (stop) A.conv_step = smp;
+        if (stop || mode == 1) write_averages(s_ctl, rp, A);
+      }
     }
+    s_lam = lam;
+    s_stop = stop;
   }
   __syncthreads();
   if (first && step > 1 && threadIdx.x >= 64 && threadIdx.x < 128) {
@@ -503,60 +481,155 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(Params p, Buffers b, int3
     double *dst = reinterpret_cast<double *>(&b.acc[r]);
     for (int t = (int)threadIdx.x - 64; t < kAccWords; t += 64) dst[t] = src[t];
   }
-  const bool step_on = mode != 1 && !s_stop;
-  if (!mob) {  // fixed or padding atom: v = 0, never moves
-    if (p.msum && step_on && grp != kPad) {
-      b.msx[i] += x;
-      b.msy[i] += y;
-      b.msz[i] += z;
+  return StepStart{s_lam, s_stop, &s_rep};
+}
+
+// A replica whose running averages converged in an earlier launch stays
+// frozen (the whole block leaves together).  One that converges in this
+// launch (at sample step - 1, written by its first block while others may
+// still be starting) still takes this launch's lambda.
+__device__ __forceinline__ bool frozen(const Params &p, const Buffers &b, int r, int64_t step) {
+  if (!p.conv) return false;
+  const int64_t cs = b.acc[r].conv_step;
+  return cs != 0 && cs < step - 1;
+}
+
+// Per-atom state of the kick-drift (loaded early by the caller, so that the
+// loads stay in flight while the slots are reduced).  Every array covers
+// the padded range, so these loads need not wait for the group.
+struct KickAtom {
+  uint8_t grp;
+  double x, y, z, vx, vy, vz, fx, fy, fz;
+  float xr, yr, zr;
+};
+
+__device__ __forceinline__ KickAtom kick_load(const Buffers &b, int64_t i, bool full) {
+  KickAtom a;
+  a.grp = b.group[i];
+  a.vx = b.vx[i];
+  a.vy = b.vy[i];
+  a.vz = b.vz[i];
+  a.x = a.y = a.z = a.fx = a.fy = a.fz = 0.0;
+  a.xr = a.yr = a.zr = 0.f;
+  if (full) {
+    a.fx = b.fx[i]; a.fy = b.fy[i]; a.fz = b.fz[i];
+    a.x = b.x[i]; a.y = b.y[i]; a.z = b.z[i];
+    a.xr = b.xr[i]; a.yr = b.yr[i]; a.zr = b.zr[i];
+  }
+  return a;
+}
+
+// v <- lambda v, then (step_on) v += dt/(2m) F and x += dt v for one atom;
+// the escape and skin checks and the position sums.  point: a list rebuild
+// point of the kick-drift graphs follows this step (the trigger test
+// replaces the skin check).  store: this thread writes the atom back (the
+// gather copy with w = 0 only when gather is set).  The updated state stays
+// in a.
+template <class R>
+__device__ __forceinline__ void kick_atom(const Params &p, const Buffers &b, int64_t i, KickAtom &a, double lam,
+                                          bool step_on, bool point, const RepInfo &rp, bool store, bool gather) {
+  using V4 = typename V4T<R>::T;
+  if (!moves_z(p, a.grp)) {  // fixed or padding atom: v = 0, never moves
+    if (store && p.msum && step_on && a.grp != kPad) {
+      b.msx[i] += a.x;
+      b.msy[i] += a.y;
+      b.msz[i] += a.z;
     }
     return;
   }
-  const double lam = s_lam;
-  vx *= lam;
-  vy *= lam;
-  vz *= lam;
-  if (zonly) fx = fy = 0.0;  // held along x and y
+  a.vx *= lam;
+  a.vy *= lam;
+  a.vz *= lam;
+  if (a.grp != 0) a.fx = a.fy = 0.0;  // a moving atom of the top region: along z only
   if (step_on) {
-    vx += p.hdt_m * fx;
-    vy += p.hdt_m * fy;
-    vz += p.hdt_m * fz;
-    x += p.dt * vx;
-    y += p.dt * vy;
-    z += p.dt * vz;
-    b.x[i] = x;
-    b.y[i] = y;
-    b.z[i] = z;
-    // gather copy for the pair kernels; w (B') is rewritten by the density pass
-    V4 v4;
-    v4.x = (R)x;
-    v4.y = (R)y;
-    v4.z = (R)z;
-    v4.w = (R)0;
-    reinterpret_cast<V4 *>(b.pos4)[i] = v4;
-    const double cx = x - s_rep.center[0], cy = y - s_rep.center[1], cz = z - s_rep.center[2];
-    if (!(cx * cx + cy * cy + cz * cz <= p.esc2)) set_err(b, isfinite(x + y + z) ? E_ESCAPE : E_NONFINITE);
-    const double ex = x - (double)xr, ey = y - (double)yr, ez = z - (double)zr;
-    const double e2 = ex * ex + ey * ey + ez * ez;
-    if (mode == 2) {
-      // A rebuild point: the lists must last until the next one.  Rebuild
-      // before this step's density pass if this atom's displacement since
-      // the build, plus what its speed (with 50% headroom) adds over the
-      // steps in between, reaches the limit (which also covers an atom
-      // already past half the skin).
-      if (sqrt(e2) + p.trig_v * sqrt(vx * vx + vy * vy + vz * vz) > p.trig_lim) atomicOr(&b.ctl->rebuild, 1);
-    } else if (e2 > p.half_skin2) {
-      set_err(b, E_SKIN);  // the lists this step will use are no longer valid
-    }
-    if (p.msum) {  // Eq. (mean_pos): this step's positions are sample s's
-      b.msx[i] += x;
-      b.msy[i] += y;
-      b.msz[i] += z;
+    a.vx += p.hdt_m * a.fx;
+    a.vy += p.hdt_m * a.fy;
+    a.vz += p.hdt_m * a.fz;
+    a.x += p.dt * a.vx;
+    a.y += p.dt * a.vy;
+    a.z += p.dt * a.vz;
+    if (store) {
+      b.x[i] = a.x;
+      b.y[i] = a.y;
+      b.z[i] = a.z;
+      if (gather) {
+        // gather copy for the pair kernels; w (B') is rewritten by the density pass
+        V4 v4;
+        v4.x = (R)a.x;
+        v4.y = (R)a.y;
+        v4.z = (R)a.z;
+        v4.w = (R)0;
+        reinterpret_cast<V4 *>(b.pos4)[i] = v4;
+      }
+      const double cx = a.x - rp.center[0], cy = a.y - rp.center[1], cz = a.z - rp.center[2];
+      if (!(cx * cx + cy * cy + cz * cz <= p.esc2)) set_err(b, isfinite(a.x + a.y + a.z) ? E_ESCAPE : E_NONFINITE);
+      const double ex = a.x - (double)a.xr, ey = a.y - (double)a.yr, ez = a.z - (double)a.zr;
+      const double e2 = ex * ex + ey * ey + ez * ez;
+      if (point) {
+        // A rebuild point: the lists must last until the next one.  Rebuild
+        // before this step's density pass if this atom's displacement since
+        // the build, plus what its speed (with 50% headroom) adds over the
+        // steps in between, reaches the limit (which also covers an atom
+        // already past half the skin).
+        if (sqrt(e2) + p.trig_v * sqrt(a.vx * a.vx + a.vy * a.vy + a.vz * a.vz) > p.trig_lim)
+          atomicOr(&b.ctl->rebuild, 1);
+      } else if (e2 > p.half_skin2) {
+        set_err(b, E_SKIN);  // the lists this step will use are no longer valid
+      }
+      if (p.msum) {  // Eq. (mean_pos): this step's positions are sample s's
+        b.msx[i] += a.x;
+        b.msy[i] += a.y;
+        b.msz[i] += a.z;
+      }
     }
   }
-  b.vx[i] = vx;
-  b.vy[i] = vy;
-  b.vz[i] = vz;
+  if (store) {
+    b.vx[i] = a.vx;
+    b.vy[i] = a.vy;
+    b.vz[i] = a.vz;
+  }
+}
+
+// Position of an atom after the next kick-drift taken with lambda = 1:
+// x + dt (v + dt/(2m) F), in the pair arithmetic's type.  The mixed form's
+// density pass forms its neighbours' positions from it; the true step
+// differs by (lambda - 1) dt v, ~1e-6 A (|lambda - 1| ~ 1e-4, |v| dt ~
+// 0.015 A), below the FP32 resolution of the coordinates (7.6e-6 A at 100 A).
+template <class R>
+__device__ __forceinline__ typename V4T<R>::T next_position(const Params &p, uint8_t g, double x, double y, double z,
+                                                            double vx, double vy, double vz, double fx, double fy,
+                                                            double fz) {
+  typename V4T<R>::T n;
+  if (moves_z(p, g)) {
+    if (g != 0) fx = fy = 0.0;
+    x += p.dt * (vx + p.hdt_m * fx);
+    y += p.dt * (vy + p.hdt_m * fy);
+    z += p.dt * (vz + p.hdt_m * fz);
+  }
+  n.x = (R)x;
+  n.y = (R)y;
+  n.z = (R)z;
+  n.w = (R)0;
+  return n;
+}
+
+// ---------------------------------------------------------------------------
+// kick-drift (mode 0; mode 2: a list rebuild point follows) / finalize
+// (mode 1).  The mixed form folds the kick-drift into the density pass and
+// launches this kernel only to finalize.
+// ---------------------------------------------------------------------------
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_kick_drift(Params p, Buffers b, int32_t k, int32_t mode) {
+  const int64_t tile = blockIdx.x;
+  const int r = (p.n_rep == 1) ? 0 : b.blk_rep[tile];
+  const int64_t i = tile * kTile + threadIdx.x;
+  KickAtom a = kick_load(b, i, mode != 1);
+  const int64_t step = b.ctl->base + k;  // mode 0, 2: step being computed; mode 1: n_steps + 1
+  if (frozen(p, b, r, step)) return;
+  const bool first = p.n_rep == 1 ? tile == 0 : (tile == 0 || b.blk_rep[tile - 1] != r);
+  const StepStart st = step_start(p, b, r, step, first, mode);
+  const bool step_on = mode != 1 && !st.stop;
+  kick_atom<R>(p, b, i, a, st.lam, step_on, mode == 2, *st.rep, true, true);
 }
 
 // gather copy of positions (x, y, z, keep w) for the pair kernels
