@@ -232,9 +232,12 @@ __global__ void k_burst_begin(Buffers b, int n_rep, int64_t ntot) {
   for (size_t t = t0; t < nslot; t += (size_t)gridDim.x * blockDim.x) b.slots[t] = 0ull;
   if (b.msx)
     for (size_t t = t0; t < (size_t)ntot; t += (size_t)gridDim.x * blockDim.x) b.msx[t] = b.msy[t] = b.msz[t] = 0.0;
-  const size_t nacc = (size_t)n_rep * (sizeof(RepAcc) / sizeof(double));
+  // accumulators zero; the last lambda 1 (no thermostat step taken yet)
+  constexpr size_t kAccWords = sizeof(RepAcc) / sizeof(double);
+  constexpr size_t kLamWord = offsetof(RepAcc, lam_last) / sizeof(double);
+  const size_t nacc = (size_t)n_rep * kAccWords;
   double *acc = reinterpret_cast<double *>(b.acc);
-  for (size_t t = t0; t < nacc; t += (size_t)gridDim.x * blockDim.x) acc[t] = 0.0;
+  for (size_t t = t0; t < nacc; t += (size_t)gridDim.x * blockDim.x) acc[t] = (t % kAccWords == kLamWord) ? 1.0 : 0.0;
   if (t0 == 0) b.ctl->err = 0;
 }
 
@@ -347,14 +350,16 @@ __device__ void write_averages(const Control &c, const RepInfo &rp, RepAcc &A) {
   for (int q = 0; q < 3; ++q) {
     double se = NAN;
     if (nb >= 2) {
-      double mu = 0.0, m[kSEBlocks];
-      for (int k = 0; k < nb; ++k) {
-        m[k] = A.blk[k][q] / (double)bs;
-        mu += m[k];
-      }
+      // two passes over the batch sums (no array of means: this code shares
+      // its kernels' register budget)
+      double mu = 0.0;
+      for (int k = 0; k < nb; ++k) mu += A.blk[k][q] / (double)bs;
       mu /= (double)nb;
       double v = 0.0;
-      for (int k = 0; k < nb; ++k) v += (m[k] - mu) * (m[k] - mu);
+      for (int k = 0; k < nb; ++k) {
+        const double d = A.blk[k][q] / (double)bs - mu;
+        v += d * d;
+      }
       se = sqrt(v / (double)(nb * (nb - 1)));
     }
     A.out[4 + q] = se;
@@ -590,21 +595,27 @@ __device__ __forceinline__ void kick_atom(const Params &p, const Buffers &b, int
   }
 }
 
-// Position of an atom after the next kick-drift taken with lambda = 1:
-// x + dt (v + dt/(2m) F), in the pair arithmetic's type.  The mixed form's
-// density pass forms its neighbours' positions from it; the true step
-// differs by (lambda - 1) dt v, ~1e-6 A (|lambda - 1| ~ 1e-4, |v| dt ~
-// 0.015 A), below the FP32 resolution of the coordinates (7.6e-6 A at 100 A).
+// Position of an atom after the next kick-drift, x + dt (lp v + dt/(2m) F),
+// in the pair arithmetic's type, with lp a prediction of the next step's
+// lambda: the last one taken (RepAcc::lam_last; 1 before the second step,
+// where lambda is 1 exactly).  The mixed form's density pass forms its
+// neighbours' positions from it.  The true step differs by (lambda - lp)
+// dt v: lambda changes by (dt/tau) T0 dT / (2 T^2) per step, up to ~1e-4
+// where a burst's start drains a tenth of the kinetic energy per 10 fs,
+// ~1e-6 or less in equilibrium; times |v| dt ~ 0.015 A that is ~1e-6 A at
+// most, below the FP32 resolution of the coordinates (7.6e-6 A at 100 A).
+// (lp = 1 would be off by |lambda - 1| dt |v|, up to 1e-4 A early in a
+// burst, where T is far from T0.)
 template <class R>
-__device__ __forceinline__ typename V4T<R>::T next_position(const Params &p, uint8_t g, double x, double y, double z,
-                                                            double vx, double vy, double vz, double fx, double fy,
-                                                            double fz) {
+__device__ __forceinline__ typename V4T<R>::T next_position(const Params &p, uint8_t g, double lp, double x, double y,
+                                                            double z, double vx, double vy, double vz, double fx,
+                                                            double fy, double fz) {
   typename V4T<R>::T n;
   if (moves_z(p, g)) {
     if (g != 0) fx = fy = 0.0;
-    x += p.dt * (vx + p.hdt_m * fx);
-    y += p.dt * (vy + p.hdt_m * fy);
-    z += p.dt * (vz + p.hdt_m * fz);
+    x += p.dt * (lp * vx + p.hdt_m * fx);
+    y += p.dt * (lp * vy + p.hdt_m * fy);
+    z += p.dt * (lp * vz + p.hdt_m * fz);
   }
   n.x = (R)x;
   n.y = (R)y;
@@ -632,18 +643,28 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(Params p, Buffers b, int3
   kick_atom<R>(p, b, i, a, st.lam, step_on, mode == 2, *st.rep, true, true);
 }
 
-// gather copy of positions (x, y, z, keep w) for the pair kernels
+// gather copy of positions (x, y, z, keep w) for the pair kernels, and in
+// the mixed form the positions after the next drift (after a sort, a
+// roll-back or new state: the state they derive from changed)
 template <class R>
-__global__ __launch_bounds__(kBlock) void k_pos4(Buffers b) {
+__global__ __launch_bounds__(kBlock) void k_pos4(Params p, Buffers b) {
   using V4 = typename V4T<R>::T;
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (b.group[i] == kPad) return;
+  const uint8_t g = b.group[i];
+  if (g == kPad) return;
   V4 *p4 = reinterpret_cast<V4 *>(b.pos4);
   V4 v = p4[i];
-  v.x = (R)b.x[i];
-  v.y = (R)b.y[i];
-  v.z = (R)b.z[i];
+  const double x = b.x[i], y = b.y[i], z = b.z[i];
+  v.x = (R)x;
+  v.y = (R)y;
+  v.z = (R)z;
   p4[i] = v;
+  if (p.fold) {
+    // between the chunks of a burst: the same prediction the last force pass used
+    const int r = b.blk_rep[i / kTile];
+    reinterpret_cast<V4 *>(b.pnext)[i] =
+        next_position<R>(p, g, b.acc[r].lam_last, x, y, z, b.vx[i], b.vy[i], b.vz[i], b.fx[i], b.fy[i], b.fz[i]);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -779,7 +800,8 @@ __device__ void build_one(const Params &p, const Buffers &b, int64_t i, int lane
 }
 
 // Grid-stride over atoms: KB lanes per atom.  cond != 0: a rebuild point
-// inside a chunk, which builds only when a kick-drift asked for it.
+// inside a chunk, which builds only when the step before asked for it (its
+// kick-drift, or in the mixed form the force pass before that).
 template <class R, int LPA>
 __global__ __launch_bounds__(kBlock) void k_build(Params p, Buffers b, int32_t cond) {
   if (cond) {
@@ -792,6 +814,15 @@ __global__ __launch_bounds__(kBlock) void k_build(Params p, Buffers b, int32_t c
     if (b.group[i] != kPad) build_one<R, LPA>(p, b, i, lane);  // a lane group skips together
 }
 
+// In the mixed form (p.fold) the step's kick-drift is done here too.  The
+// pair loop takes every position, the atom's own included, from
+// Buffers::pnext, which the previous force pass wrote (the position after
+// this step's drift, with the last lambda taken for this step's), so it
+// needs neither lambda nor any other atom's update and starts at once.  After it, every block takes
+// lambda from the slot sums (the replica's first block also records the
+// sample) and each atom's lanes update it exactly (lane 0 stores, the gather
+// copy with its B').  One kernel boundary less per step.  Step 0 (forces
+// at a burst's start) is the plain density pass.
 template <class R, int LPA, int NM>
 __global__ __launch_bounds__(kBlock) void k_density(Params p, Buffers b, int32_t k) {
   using V4 = typename V4T<R>::T;
@@ -802,31 +833,35 @@ __global__ __launch_bounds__(kBlock) void k_density(Params p, Buffers b, int32_t
   const int r = b.blk_rep[tile];
   const int64_t step = b.ctl->base + k;
   const int par = (int)(step & 1);
-  {
+  const bool fold = p.fold && step >= 1;
+  if (!p.fold) {
     // the slots of the other parity were consumed by this step's kick-drift
+    // (in the mixed form the force pass clears them: this pass reads them)
     const size_t nz = (size_t)p.n_rep * kSlots * kNQ;
     unsigned long long *zp = b.slots + (size_t)(par ^ 1) * nz;
     for (size_t t = (size_t)gt; t < nz; t += (size_t)gridDim.x * kBlock) zp[t] = 0ull;
   }
   // every block of a conditional build has read the request: clear it
   if (gt == 0 && b.ctl->rebuild != 0) atomicAnd(&b.ctl->rebuild, 0);
-  if (p.conv && b.acc[r].conv_step != 0) return;  // converged replica: frozen
+  if (fold ? frozen(p, b, r, step) : (p.conv && b.acc[r].conv_step != 0)) return;  // converged replica: frozen
   const uint8_t g = b.group[i];
   const bool real = g != kPad;
   const V4 *p4 = reinterpret_cast<const V4 *>(b.pos4);
+  const V4 *pn = fold ? reinterpret_cast<const V4 *>(b.pnext) : p4;  // positions of the pair terms
+  V4 pi;
+  if (real) pi = pn[i];
   // Sutton-Chen: sum of (a/r)^m, of r and the pair count; the shift
   // rho_s = (a/r)^m - rhoc - (r - rc) drhoc is applied once per atom.
   // Tables: the sum of the interpolated rho.
   R acc = (R)0, sr = (R)0;
   int np = 0;
   if (real) {
-    const V4 pi = p4[i];
     const R rc2 = (R)p.rc2, a = (R)p.a;
     // slots per lane: the list is padded with the far-away sentinel to whole
     // passes, so every slot of a pass holds a valid index
     const int npl = pass_slots<LPA>(b.ncount[i]);
     const int4 *nb4 = reinterpret_cast<const int4 *>(b.nbr) + (size_t)i * LPA + lane;
-    pair_passes(p4, nb4, p.nbr_stride, npl, [&](const V4(&pj)[8]) {
+    pair_passes(pn, nb4, p.nbr_stride, npl, [&](const V4(&pj)[8]) {
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const R dx = pj[u].x - pi.x, dy = pj[u].y - pi.y, dz = pj[u].z - pi.z;
@@ -855,6 +890,22 @@ __global__ __launch_bounds__(kBlock) void k_density(Params p, Buffers b, int32_t
       np += __shfl_xor(np, o);
     }
   }
+  if (fold) {
+    // the atom's own state is loaded after lambda: not held through the pair
+    // loop or the slot reduction, which keeps the kernel's register count
+    // (and so its occupancy) at that of the plain pass
+    const int64_t a0 = (int64_t)blockIdx.x * (kBlock / LPA);  // the block's first atom
+    const bool first = a0 % kTile == 0 && (tile == 0 || b.blk_rep[tile - 1] != r);
+    const StepStart st = step_start(p, b, r, step, first, 0);
+    KickAtom at = kick_load(b, i, true);
+    // a replica whose averages converged at this step's sample keeps its
+    // state after lambda (no drift); the rest of this step is not needed
+    kick_atom<R>(p, b, i, at, st.lam, !st.stop, false, *st.rep, lane == 0, false);
+    if (st.stop) return;
+    pi.x = (R)at.x;
+    pi.y = (R)at.y;
+    pi.z = (R)at.z;
+  }
   long long q[1] = {0};
   if (lane == 0 && real) {
     double rb = (double)acc;
@@ -868,7 +919,14 @@ __global__ __launch_bounds__(kBlock) void k_density(Params p, Buffers b, int32_t
       Bp = -0.5 * p.c_eps / sq;
     }
     // the force pass reads B' (tables) or -m B' (Sutton-Chen, one product less per pair)
-    reinterpret_cast<R *>(b.pos4)[4 * i + 3] = (R)(NM == 2 ? Bp : -(double)p.m * Bp);
+    const R wv = (R)(NM == 2 ? Bp : -(double)p.m * Bp);
+    if (fold && moves_z(p, g)) {  // the gather copy of the moved atom, with its B'
+      V4 v4 = pi;
+      v4.w = wv;
+      reinterpret_cast<V4 *>(b.pos4)[i] = v4;
+    } else {
+      reinterpret_cast<R *>(b.pos4)[4 * i + 3] = wv;
+    }
     q[0] = to_fix(B);
   }
   block_atoms_add<1, kBlock / LPA>(q, lane == 0, threadIdx.x / LPA,
@@ -876,7 +934,8 @@ __global__ __launch_bounds__(kBlock) void k_density(Params p, Buffers b, int32_t
 }
 
 // ---------------------------------------------------------------------------
-// force pass: mode 0 = step (second half kick + sums), 1 = forces only
+// force pass: mode 0 = step (second half kick + sums), 1 = forces only,
+// 2 = step, and the next step is a list rebuild point of the mixed form
 // ---------------------------------------------------------------------------
 template <class R, int LPA, int NM>
 __global__ __launch_bounds__(kBlock) void k_force(Params p, Buffers b, int32_t k, int32_t mode) {
@@ -889,6 +948,13 @@ __global__ __launch_bounds__(kBlock) void k_force(Params p, Buffers b, int32_t k
   const int r = b.blk_rep[tile];
   const int64_t step = b.ctl->base + k;
   const int par = (int)(step & 1);
+  if (p.fold) {
+    // mixed form: the slots of the other parity were read by this step's
+    // density pass (its kick-drift part); the next step's adds into them
+    const size_t nz = (size_t)p.n_rep * kSlots * kNQ;
+    unsigned long long *zp = b.slots + (size_t)(par ^ 1) * nz;
+    for (size_t t = (size_t)gt; t < nz; t += (size_t)gridDim.x * kBlock) zp[t] = 0ull;
+  }
   if (p.conv && b.acc[r].conv_step != 0) return;  // converged replica: frozen
   const uint8_t g = b.group[i];
   const bool real = g != kPad;
@@ -968,9 +1034,12 @@ __global__ __launch_bounds__(kBlock) void k_force(Params p, Buffers b, int32_t k
     b.fy[i] = Fy;
     b.fz[i] = Fz;
     if (!isfinite(Fx + Fy + Fz)) set_err(b, E_NONFINITE);
+    double vx = 0.0, vy = 0.0, vz = 0.0;
     if (moves_z(p, g)) {
-      double vx = b.vx[i], vy = b.vy[i], vz = b.vz[i];
-      if (mode == 0) {
+      vx = b.vx[i];
+      vy = b.vy[i];
+      vz = b.vz[i];
+      if (mode != 1) {
         if (g == 0) {
           vx += p.hdt_m * Fx;
           vy += p.hdt_m * Fy;
@@ -982,6 +1051,20 @@ __global__ __launch_bounds__(kBlock) void k_force(Params p, Buffers b, int32_t k
       }
       q[Q_MV2] = to_fix(p.mvv2e_m * (vx * vx + vy * vy + vz * vz));
       q[Q_MVZ2] = to_fix(p.mvv2e_m * vz * vz);
+    }
+    if (p.fold) {
+      // mixed form: where the next step's drift takes the atom, for the next
+      // density pass (forces only: a burst's first step, lambda 1); and,
+      // before a rebuild point, whether the lists last until the one after
+      // it (from here, over m steps)
+      const double x = b.x[i], y = b.y[i], z = b.z[i];
+      const double lp = mode == 1 ? 1.0 : b.acc[r].lam_last;
+      reinterpret_cast<V4 *>(b.pnext)[i] = next_position<R>(p, g, lp, x, y, z, vx, vy, vz, Fx, Fy, Fz);
+      if (mode == 2 && moves_z(p, g)) {
+        const double ex = x - (double)b.xr[i], ey = y - (double)b.yr[i], ez = z - (double)b.zr[i];
+        if (sqrt(ex * ex + ey * ey + ez * ez) + p.trig_v * sqrt(vx * vx + vy * vy + vz * vz) > p.trig_lim)
+          atomicOr(&b.ctl->rebuild, 1);
+      }
     }
     // pair energy of the atom: tables sum V; Sutton-Chen sums -n V, r and the count
     const double epair = (NM == 2) ? (double)ep
@@ -1420,8 +1503,8 @@ void launch_kick_drift(const Params &p, const Buffers &b, int precision, int32_t
 }
 
 void launch_pos4(const Params &p, const Buffers &b, int precision, hipStream_t s) {
-  if (precision) hipLaunchKernelGGL(k_pos4<float>, dim3(tiles(p)), dim3(kBlock), 0, s, b);
-  else hipLaunchKernelGGL(k_pos4<double>, dim3(tiles(p)), dim3(kBlock), 0, s, b);
+  if (precision) hipLaunchKernelGGL(k_pos4<float>, dim3(tiles(p)), dim3(kBlock), 0, s, p, b);
+  else hipLaunchKernelGGL(k_pos4<double>, dim3(tiles(p)), dim3(kBlock), 0, s, p, b);
 }
 
 template <class R, int NM>

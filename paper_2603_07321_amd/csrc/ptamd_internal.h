@@ -124,13 +124,14 @@ struct Params {
   double tab_inv_dr;   // 1 / dr
   double tab_inv_drho; // 1 / drho
   int32_t tab_nrho;
-  int32_t pad3;
+  int32_t fold;        // nonzero (mixed form): the density pass does the step's kick-drift (Buffers::pnext)
 };
 
 // Device buffers (pointers), passed by value.
 struct Buffers {
   double *x, *y, *z, *vx, *vy, *vz, *fx, *fy, *fz;
   void *pos4;          // float4 or double4: x, y, z, B'
+  void *pnext;         // mixed form: float4 x + dt (v + dt F / 2m), the position after the next step at lambda = 1
   uint8_t *group;
   int32_t *orig;       // original global index of each sorted atom
   int32_t *cell;       // linear cell index (within the replica grid) at the last sort
