@@ -374,6 +374,18 @@ __device__ void write_averages(const Control &c, const RepInfo &rp, RepAcc &A) {
 // completes and the convergence decision (shared by the kick-drift and the
 // density pass that takes the kick-drift over in the mixed form)
 // ---------------------------------------------------------------------------
+// Berendsen's lambda from the replica's kinetic sum (fixed point, summed
+// over the 64 slots): lambda^2 = 1 + (dt/tau)(T0/T - 1).  False (and
+// lambda 1) where that needs T > 0 or gives a negative square.  Every path
+// that takes lambda calls this one function, so they agree bit for bit.
+__device__ __forceinline__ bool thermostat_lambda(const Params &p, const RepInfo &rp, long long qmv2, double *lam) {
+  const double T = ((double)qmv2 / kFix) / (rp.dof * p.kb);
+  const double l2 = 1.0 + (p.dt / p.tau) * (rp.T0 / T - 1.0);
+  const bool ok = T > 0.0 && l2 >= 0.0;
+  *lam = ok ? sqrt(l2) : 1.0;
+  return ok;
+}
+
 struct StepStart {
   double lam;          // thermostat factor of the previous step (1 at step 1)
   int stop;            // the replica's averages converged at this step's sample
@@ -447,15 +459,7 @@ __device__ StepStart step_start(const Params &p, const Buffers &b, int r, int64_
       double qd[6];
       for (int t = 0; t < 6; ++t) qd[t] = (double)q[t] / kFix;
       const RepInfo &rp = s_rep;
-      if (p.thermostat) {
-        const double T = qd[Q_MV2] / (rp.dof * p.kb);
-        const double l2 = 1.0 + (p.dt / p.tau) * (rp.T0 / T - 1.0);
-        if (!(T > 0.0) || !(l2 >= 0.0)) {
-          if (first) set_err(b, E_STATE);
-        } else {
-          lam = sqrt(l2);
-        }
-      }
+      if (p.thermostat && !thermostat_lambda(p, rp, q[Q_MV2], &lam) && first) set_err(b, E_STATE);
       const int64_t smp = step - 1;  // the sample this launch completes
       const int64_t lag = p.conv ? s_ctl.conv_lag : 0;
       const bool check = lag > 0 && smp % lag == 0;
@@ -850,6 +854,17 @@ __global__ __launch_bounds__(kBlock) void k_density(Params p, Buffers b, int32_t
   const V4 *pn = fold ? reinterpret_cast<const V4 *>(b.pnext) : p4;  // positions of the pair terms
   V4 pi;
   if (real) pi = pn[i];
+  // folded step: this lane's slot of the previous step's kinetic sum and
+  // the atom's state, read ahead of the pair loop (the force pass that wrote
+  // them has finished), so that the kick after it waits on no load.  The
+  // registers this holds limit the kernel to 5 wavefronts per SIMD; the
+  // folded sizes (up to 131,072 atoms) launch at most 8 at 4 lanes per atom
+  // and 4 at 2, where the latency hidden outweighs the residency lost.
+  long long qk = 0;
+  if (fold && step > 1 && p.thermostat)
+    qk = (long long)slot_row(b, p.n_rep, (int)((step - 1) & 1), r, (int)(threadIdx.x & 63))[Q_MV2];
+  KickAtom at{};
+  if (fold) at = kick_load(b, i, true);
   // Sutton-Chen: sum of (a/r)^m, of r and the pair count; the shift
   // rho_s = (a/r)^m - rhoc - (r - rc) drhoc is applied once per atom.
   // Tables: the sum of the interpolated rho.
@@ -891,17 +906,29 @@ __global__ __launch_bounds__(kBlock) void k_density(Params p, Buffers b, int32_t
     }
   }
   if (fold) {
-    // the atom's own state is loaded after lambda: not held through the pair
-    // loop or the slot reduction, which keeps the kernel's register count
-    // (and so its occupancy) at that of the plain pass
     const int64_t a0 = (int64_t)blockIdx.x * (kBlock / LPA);  // the block's first atom
     const bool first = a0 % kTile == 0 && (tile == 0 || b.blk_rep[tile - 1] != r);
-    const StepStart st = step_start(p, b, r, step, first, 0);
-    KickAtom at = kick_load(b, i, true);
+    const int64_t lag = p.conv ? b.ctl->conv_lag : 0;
+    const bool check = lag > 0 && (step - 1) % lag == 0;  // all blocks take the convergence decision
+    double lam = 1.0;
+    int stop = 0;
+    const RepInfo *rp = &b.rep[r];
+    if (first || check) {  // uniform over the block
+      const StepStart st = step_start(p, b, r, step, first, 0);
+      lam = st.lam;
+      stop = st.stop;
+      rp = st.rep;
+    } else if (step > 1 && p.thermostat) {
+      // the other blocks need lambda only: each wavefront sums the 64 slots
+      // itself, with neither barrier nor LDS
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) qk += shfl_xor_ll(qk, o);
+      thermostat_lambda(p, *rp, qk, &lam);
+    }
     // a replica whose averages converged at this step's sample keeps its
     // state after lambda (no drift); the rest of this step is not needed
-    kick_atom<R>(p, b, i, at, st.lam, !st.stop, false, *st.rep, lane == 0, false);
-    if (st.stop) return;
+    kick_atom<R>(p, b, i, at, lam, !stop, false, *rp, lane == 0, false);
+    if (stop) return;
     pi.x = (R)at.x;
     pi.y = (R)at.y;
     pi.z = (R)at.z;
@@ -958,6 +985,13 @@ __global__ __launch_bounds__(kBlock) void k_force(Params p, Buffers b, int32_t k
   if (p.conv && b.acc[r].conv_step != 0) return;  // converged replica: frozen
   const uint8_t g = b.group[i];
   const bool real = g != kPad;
+  // mixed form: the state the epilogue needs for the next position, read
+  // ahead of the pair loop
+  double x = 0.0, y = 0.0, z = 0.0, vx = 0.0, vy = 0.0, vz = 0.0;
+  if (p.fold && real && lane == 0) {
+    x = b.x[i]; y = b.y[i]; z = b.z[i];
+    vx = b.vx[i]; vy = b.vy[i]; vz = b.vz[i];
+  }
   const V4 *p4 = reinterpret_cast<const V4 *>(b.pos4);
   // Sutton-Chen, with w_j = -m B'_j from the density pass:
   //   dU/dr = [-n eps (a/r)^n + (w_i + w_j) (a/r)^m] / r - (dVc - (w_i + w_j) drhoc / m)
@@ -1034,11 +1068,12 @@ __global__ __launch_bounds__(kBlock) void k_force(Params p, Buffers b, int32_t k
     b.fy[i] = Fy;
     b.fz[i] = Fz;
     if (!isfinite(Fx + Fy + Fz)) set_err(b, E_NONFINITE);
-    double vx = 0.0, vy = 0.0, vz = 0.0;
     if (moves_z(p, g)) {
-      vx = b.vx[i];
-      vy = b.vy[i];
-      vz = b.vz[i];
+      if (!p.fold) {
+        vx = b.vx[i];
+        vy = b.vy[i];
+        vz = b.vz[i];
+      }
       if (mode != 1) {
         if (g == 0) {
           vx += p.hdt_m * Fx;
@@ -1057,7 +1092,6 @@ __global__ __launch_bounds__(kBlock) void k_force(Params p, Buffers b, int32_t k
       // density pass (forces only: a burst's first step, lambda 1); and,
       // before a rebuild point, whether the lists last until the one after
       // it (from here, over m steps)
-      const double x = b.x[i], y = b.y[i], z = b.z[i];
       const double lp = mode == 1 ? 1.0 : b.acc[r].lam_last;
       reinterpret_cast<V4 *>(b.pnext)[i] = next_position<R>(p, g, lp, x, y, z, vx, vy, vz, Fx, Fy, Fz);
       if (mode == 2 && moves_z(p, g)) {
