@@ -123,6 +123,10 @@ typedef struct {
     int64_t steps;           /* MD steps since creation */
     double skin;
     double bin_margin;
+    int32_t list_index_bits; /* 16: list entries are 16-bit offsets j - i; 32: indices (a system
+                                switches for good when a list build meets an offset beyond 16 bits) */
+    int32_t folded;          /* 1: each step's kick-drift runs inside its density pass (mixed form,
+                                up to 131,072 padded atoms) */
 } ptamd_info;
 
 /* ---- creation ---- */

@@ -119,10 +119,33 @@ __device__ __forceinline__ void gather8(const V4 *p4, int4 la, int4 lb, V4 (&pj)
 // issue order.  (Gathering the next pass's positions ahead as well, into a
 // second buffer, measured slower on the 62,500-atom cube.)  body(pj)
 // evaluates eight gathered entries.
-template <class V4, class Body>
-__device__ __forceinline__ void pair_passes(const V4 *p4, const int4 *nb4, int64_t stride, int npl, Body &&body) {
-  int4 la = nb4[0], lb = nb4[stride];
+// Index of a 16-bit list entry w of atom self (sent: the sentinel's).
+__device__ __forceinline__ int off_index(int w, int self, int sent) {
+  return w == kOffSentinel ? sent : self + w;
+}
+
+// L16: the 16-bit form, one 16-byte group (eight offsets) per pass.
+template <bool L16, class V4, class Body>
+__device__ __forceinline__ void pair_passes(const V4 *p4, const int4 *nb4, int64_t stride, int npl, int self,
+                                            int sent, Body &&body) {
   V4 pj[8];
+  if (L16) {
+    int4 la = nb4[0];
+    for (int s = 0; s < npl; s += kPass) {
+      const int w[4] = {la.x, la.y, la.z, la.w};
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        pj[2 * u] = gather<V4>(p4, off_index((int)(short)(w[u] & 0xffff), self, sent));
+        pj[2 * u + 1] = gather<V4>(p4, off_index(w[u] >> 16, self, sent));
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      if (s + kPass < npl) la = nb4[(size_t)((s + kPass) / kGroup16) * stride];
+      __builtin_amdgcn_sched_barrier(0);
+      body(pj);
+    }
+    return;
+  }
+  int4 la = nb4[0], lb = nb4[stride];
   for (int s = 0; s < npl; s += kPass) {
     gather8(p4, la, lb, pj);
     __builtin_amdgcn_sched_barrier(0);
@@ -503,6 +526,31 @@ __device__ __forceinline__ bool frozen(const Params &p, const Buffers &b, int r,
   return cs != 0 && cs < step - 1;
 }
 
+// This lane's share of the replica's kinetic sum of the previous step (slot
+// lane % 64 of its column), for start_lambda; loaded early by the caller.
+__device__ __forceinline__ long long kinetic_slot(const Params &p, const Buffers &b, int r, int64_t step) {
+  if (step <= 1 || !p.thermostat) return 0;
+  return (long long)slot_row(b, p.n_rep, (int)((step - 1) & 1), r, (int)(threadIdx.x & 63))[Q_MV2];
+}
+
+// The start of a step for one block (uniform over it): the staged block
+// path of step_start where the block records the sample (the replica's
+// first block) or takes a convergence decision (every block at a
+// checkpoint); elsewhere lambda only, summed by each wavefront from the
+// slot values its lanes loaded (kinetic_slot), with neither barrier nor LDS.
+__device__ __forceinline__ StepStart start_lambda(const Params &p, const Buffers &b, int r, int64_t step, bool first,
+                                                  int32_t mode, long long qk) {
+  const int64_t lag = p.conv ? b.ctl->conv_lag : 0;
+  if (first || (lag > 0 && (step - 1) % lag == 0)) return step_start(p, b, r, step, first, mode);
+  StepStart st{1.0, 0, &b.rep[r]};
+  if (step > 1 && p.thermostat) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) qk += shfl_xor_ll(qk, o);
+    thermostat_lambda(p, *st.rep, qk, &st.lam);
+  }
+  return st;
+}
+
 // Per-atom state of the kick-drift (loaded early by the caller, so that the
 // loads stay in flight while the slots are reduced).  Every array covers
 // the padded range, so these loads need not wait for the group.
@@ -641,6 +689,8 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(Params p, Buffers b, int3
   KickAtom a = kick_load(b, i, mode != 1);
   const int64_t step = b.ctl->base + k;  // mode 0, 2: step being computed; mode 1: n_steps + 1
   if (frozen(p, b, r, step)) return;
+  // (lambda per wavefront, as in the folded density pass, measured no
+  // faster here: these blocks hold 256 atoms each, so there are few of them)
   const bool first = p.n_rep == 1 ? tile == 0 : (tile == 0 || b.blk_rep[tile - 1] != r);
   const StepStart st = step_start(p, b, r, step, first, mode);
   const bool step_on = mode != 1 && !st.stop;
@@ -700,7 +750,7 @@ template <class R> __device__ __forceinline__ float4 to_f4(typename V4T<R>::T v)
   return make_float4((float)v.x, (float)v.y, (float)v.z, 0.f);
 }
 
-template <class R, int LPA>
+template <class R, int LPA, bool L16>
 __device__ void build_one(const Params &p, const Buffers &b, int64_t i, int lane) {
   using V4 = typename V4T<R>::T;
   const int r = b.blk_rep[i / kTile];
@@ -783,7 +833,16 @@ __device__ void build_one(const Params &p, const Buffers &b, int64_t i, int lane
         const unsigned pos = (unsigned)cnt + (unsigned)__popcll(m & below);
         if (ok && pos < (unsigned)cap) {
           const unsigned l = pos % LPA, sl = pos / LPA;
-          b.nbr[(size_t)(sl / kGroup) * group_stride + slot_base + l * kGroup + sl % kGroup] = j;
+          if (L16) {
+            const int d = j - self;
+            const bool fits = d >= -32767 && d <= 32767;
+            if (!fits) set_err(b, E_WIDE);
+            reinterpret_cast<int16_t *>(b.nbr)[(size_t)(sl / kGroup16) * (size_t)p.nbr_stride * kGroup16 +
+                                               (size_t)self * (LPA * kGroup16) + l * kGroup16 + sl % kGroup16] =
+                (int16_t)(fits ? d : kOffSentinel);
+          } else {
+            b.nbr[(size_t)(sl / kGroup) * group_stride + slot_base + l * kGroup + sl % kGroup] = j;
+          }
         }
         cnt += __popcll(m);
       }
@@ -793,7 +852,10 @@ __device__ void build_one(const Params &p, const Buffers &b, int64_t i, int lane
   if (over) cnt = cap;
   // pad to whole passes with the sentinel (cap is a multiple of kPass * LPA)
   const int padded = (cnt + kPass * LPA - 1) / (kPass * LPA) * (kPass * LPA);
-  for (int e = cnt + lane; e < padded; e += KB) b.nbr[nbr_index(i, e, LPA, p.nbr_stride)] = (int)p.ntot;
+  for (int e = cnt + lane; e < padded; e += KB) {
+    if (L16) reinterpret_cast<int16_t *>(b.nbr)[nbr16_index(i, e, LPA, p.nbr_stride)] = (int16_t)kOffSentinel;
+    else b.nbr[nbr_index(i, e, LPA, p.nbr_stride)] = (int)p.ntot;
+  }
   if (lane == 0) {
     if (over) set_err(b, E_OVERFLOW);
     b.ncount[i] = cnt;
@@ -806,7 +868,7 @@ __device__ void build_one(const Params &p, const Buffers &b, int64_t i, int lane
 // Grid-stride over atoms: KB lanes per atom.  cond != 0: a rebuild point
 // inside a chunk, which builds only when the step before asked for it (its
 // kick-drift, or in the mixed form the force pass before that).
-template <class R, int LPA>
+template <class R, int LPA, bool L16>
 __global__ __launch_bounds__(kBlock) void k_build(Params p, Buffers b, int32_t cond) {
   if (cond) {
     if (b.ctl->rebuild == 0) return;
@@ -815,7 +877,7 @@ __global__ __launch_bounds__(kBlock) void k_build(Params p, Buffers b, int32_t c
   const int lane = (int)(threadIdx.x & (KB - 1));
   const int64_t per_pass = (int64_t)gridDim.x * (kBlock / KB);
   for (int64_t i = (int64_t)blockIdx.x * (kBlock / KB) + threadIdx.x / KB; i < p.ntot; i += per_pass)
-    if (b.group[i] != kPad) build_one<R, LPA>(p, b, i, lane);  // a lane group skips together
+    if (b.group[i] != kPad) build_one<R, LPA, L16>(p, b, i, lane);  // a lane group skips together
 }
 
 // In the mixed form (p.fold) the step's kick-drift is done here too.  The
@@ -827,7 +889,7 @@ __global__ __launch_bounds__(kBlock) void k_build(Params p, Buffers b, int32_t c
 // sample) and each atom's lanes update it exactly (lane 0 stores, the gather
 // copy with its B').  One kernel boundary less per step.  Step 0 (forces
 // at a burst's start) is the plain density pass.
-template <class R, int LPA, int NM>
+template <class R, int LPA, int NM, bool L16>
 __global__ __launch_bounds__(kBlock) void k_density(Params p, Buffers b, int32_t k) {
   using V4 = typename V4T<R>::T;
   const int64_t gt = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -860,9 +922,7 @@ __global__ __launch_bounds__(kBlock) void k_density(Params p, Buffers b, int32_t
   // registers this holds limit the kernel to 5 wavefronts per SIMD; the
   // folded sizes (up to 131,072 atoms) launch at most 8 at 4 lanes per atom
   // and 4 at 2, where the latency hidden outweighs the residency lost.
-  long long qk = 0;
-  if (fold && step > 1 && p.thermostat)
-    qk = (long long)slot_row(b, p.n_rep, (int)((step - 1) & 1), r, (int)(threadIdx.x & 63))[Q_MV2];
+  const long long qk = fold ? kinetic_slot(p, b, r, step) : 0;
   KickAtom at{};
   if (fold) at = kick_load(b, i, true);
   // Sutton-Chen: sum of (a/r)^m, of r and the pair count; the shift
@@ -876,7 +936,7 @@ __global__ __launch_bounds__(kBlock) void k_density(Params p, Buffers b, int32_t
     // passes, so every slot of a pass holds a valid index
     const int npl = pass_slots<LPA>(b.ncount[i]);
     const int4 *nb4 = reinterpret_cast<const int4 *>(b.nbr) + (size_t)i * LPA + lane;
-    pair_passes(pn, nb4, p.nbr_stride, npl, [&](const V4(&pj)[8]) {
+    pair_passes<L16>(pn, nb4, p.nbr_stride, npl, (int)i, (int)p.ntot, [&](const V4(&pj)[8]) {
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const R dx = pj[u].x - pi.x, dy = pj[u].y - pi.y, dz = pj[u].z - pi.z;
@@ -908,27 +968,11 @@ __global__ __launch_bounds__(kBlock) void k_density(Params p, Buffers b, int32_t
   if (fold) {
     const int64_t a0 = (int64_t)blockIdx.x * (kBlock / LPA);  // the block's first atom
     const bool first = a0 % kTile == 0 && (tile == 0 || b.blk_rep[tile - 1] != r);
-    const int64_t lag = p.conv ? b.ctl->conv_lag : 0;
-    const bool check = lag > 0 && (step - 1) % lag == 0;  // all blocks take the convergence decision
-    double lam = 1.0;
-    int stop = 0;
-    const RepInfo *rp = &b.rep[r];
-    if (first || check) {  // uniform over the block
-      const StepStart st = step_start(p, b, r, step, first, 0);
-      lam = st.lam;
-      stop = st.stop;
-      rp = st.rep;
-    } else if (step > 1 && p.thermostat) {
-      // the other blocks need lambda only: each wavefront sums the 64 slots
-      // itself, with neither barrier nor LDS
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) qk += shfl_xor_ll(qk, o);
-      thermostat_lambda(p, *rp, qk, &lam);
-    }
+    const StepStart st = start_lambda(p, b, r, step, first, 0, qk);
     // a replica whose averages converged at this step's sample keeps its
     // state after lambda (no drift); the rest of this step is not needed
-    kick_atom<R>(p, b, i, at, lam, !stop, false, *rp, lane == 0, false);
-    if (stop) return;
+    kick_atom<R>(p, b, i, at, st.lam, !st.stop, false, *st.rep, lane == 0, false);
+    if (st.stop) return;
     pi.x = (R)at.x;
     pi.y = (R)at.y;
     pi.z = (R)at.z;
@@ -964,7 +1008,7 @@ __global__ __launch_bounds__(kBlock) void k_density(Params p, Buffers b, int32_t
 // force pass: mode 0 = step (second half kick + sums), 1 = forces only,
 // 2 = step, and the next step is a list rebuild point of the mixed form
 // ---------------------------------------------------------------------------
-template <class R, int LPA, int NM>
+template <class R, int LPA, int NM, bool L16>
 __global__ __launch_bounds__(kBlock) void k_force(Params p, Buffers b, int32_t k, int32_t mode) {
   using V4 = typename V4T<R>::T;
   const unsigned long long t_begin = p.ktime ? wall_clock64() : 0ull;
@@ -1008,7 +1052,7 @@ __global__ __launch_bounds__(kBlock) void k_force(Params p, Buffers b, int32_t k
     // passes, so every slot of a pass holds a valid index
     const int npl = pass_slots<LPA>(b.ncount[i]);
     const int4 *nb4 = reinterpret_cast<const int4 *>(b.nbr) + (size_t)i * LPA + lane;
-    pair_passes(p4, nb4, p.nbr_stride, npl, [&](const V4(&pj)[8]) {
+    pair_passes<L16>(p4, nb4, p.nbr_stride, npl, (int)i, (int)p.ntot, [&](const V4(&pj)[8]) {
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const R dx = pj[u].x - pi.x, dy = pj[u].y - pi.y, dz = pj[u].z - pi.z;
@@ -1492,7 +1536,9 @@ __global__ __launch_bounds__(kBlock) void k_count_pairs(Params p, Buffers b) {
     const int cnt = b.ncount[i];
     ne = cnt;
     for (int e = 0; e < cnt; ++e) {
-      const int j = b.nbr[nbr_index(i, e, p.lpa, p.nbr_stride)];
+      const int j = p.list16 ? off_index(reinterpret_cast<const int16_t *>(b.nbr)[nbr16_index(i, e, p.lpa, p.nbr_stride)],
+                                       (int)i, (int)p.ntot)
+                           : b.nbr[nbr_index(i, e, p.lpa, p.nbr_stride)];
       const double d2 = dist2_plain(b.x[j] - b.x[i], b.y[j] - b.y[i], b.z[j] - b.z[i]);
       if (d2 < p.rc2) ++np;
     }
@@ -1541,27 +1587,27 @@ void launch_pos4(const Params &p, const Buffers &b, int precision, hipStream_t s
   else hipLaunchKernelGGL(k_pos4<double>, dim3(tiles(p)), dim3(kBlock), 0, s, p, b);
 }
 
-template <class R, int NM>
+template <class R, int NM, bool L16>
 static void density_lpa(const Params &p, const Buffers &b, int lpa, int32_t k, hipStream_t s) {
   const unsigned g = (unsigned)(p.ntot * lpa / kBlock);
   switch (lpa) {
-    case 1: hipLaunchKernelGGL((k_density<R, 1, NM>), dim3(g), dim3(kBlock), 0, s, p, b, k); break;
-    case 2: hipLaunchKernelGGL((k_density<R, 2, NM>), dim3(g), dim3(kBlock), 0, s, p, b, k); break;
-    case 4: hipLaunchKernelGGL((k_density<R, 4, NM>), dim3(g), dim3(kBlock), 0, s, p, b, k); break;
-    case 8: hipLaunchKernelGGL((k_density<R, 8, NM>), dim3(g), dim3(kBlock), 0, s, p, b, k); break;
-    default: hipLaunchKernelGGL((k_density<R, 16, NM>), dim3(g), dim3(kBlock), 0, s, p, b, k); break;
+    case 1: hipLaunchKernelGGL((k_density<R, 1, NM, L16>), dim3(g), dim3(kBlock), 0, s, p, b, k); break;
+    case 2: hipLaunchKernelGGL((k_density<R, 2, NM, L16>), dim3(g), dim3(kBlock), 0, s, p, b, k); break;
+    case 4: hipLaunchKernelGGL((k_density<R, 4, NM, L16>), dim3(g), dim3(kBlock), 0, s, p, b, k); break;
+    case 8: hipLaunchKernelGGL((k_density<R, 8, NM, L16>), dim3(g), dim3(kBlock), 0, s, p, b, k); break;
+    default: hipLaunchKernelGGL((k_density<R, 16, NM, L16>), dim3(g), dim3(kBlock), 0, s, p, b, k); break;
   }
 }
 
-template <class R, int NM>
+template <class R, int NM, bool L16>
 static void force_lpa(const Params &p, const Buffers &b, int lpa, int32_t k, int32_t mode, hipStream_t s) {
   const unsigned g = (unsigned)(p.ntot * lpa / kBlock);
   switch (lpa) {
-    case 1: hipLaunchKernelGGL((k_force<R, 1, NM>), dim3(g), dim3(kBlock), 0, s, p, b, k, mode); break;
-    case 2: hipLaunchKernelGGL((k_force<R, 2, NM>), dim3(g), dim3(kBlock), 0, s, p, b, k, mode); break;
-    case 4: hipLaunchKernelGGL((k_force<R, 4, NM>), dim3(g), dim3(kBlock), 0, s, p, b, k, mode); break;
-    case 8: hipLaunchKernelGGL((k_force<R, 8, NM>), dim3(g), dim3(kBlock), 0, s, p, b, k, mode); break;
-    default: hipLaunchKernelGGL((k_force<R, 16, NM>), dim3(g), dim3(kBlock), 0, s, p, b, k, mode); break;
+    case 1: hipLaunchKernelGGL((k_force<R, 1, NM, L16>), dim3(g), dim3(kBlock), 0, s, p, b, k, mode); break;
+    case 2: hipLaunchKernelGGL((k_force<R, 2, NM, L16>), dim3(g), dim3(kBlock), 0, s, p, b, k, mode); break;
+    case 4: hipLaunchKernelGGL((k_force<R, 4, NM, L16>), dim3(g), dim3(kBlock), 0, s, p, b, k, mode); break;
+    case 8: hipLaunchKernelGGL((k_force<R, 8, NM, L16>), dim3(g), dim3(kBlock), 0, s, p, b, k, mode); break;
+    default: hipLaunchKernelGGL((k_force<R, 16, NM, L16>), dim3(g), dim3(kBlock), 0, s, p, b, k, mode); break;
   }
 }
 
@@ -1569,43 +1615,43 @@ static bool is_al76(const Params &p) { return p.n == 7 && p.m == 6; }
 // kernel form of the potential: 2 tables, 1 Sutton-Chen n = 7 / m = 6, 0 any Sutton-Chen
 static int pot_form(const Params &p) { return p.tab ? 2 : (is_al76(p) ? 1 : 0); }
 
-template <class R>
+template <class R, bool L16>
 static void build_lpa(const Params &p, const Buffers &b, int lpa, int32_t cond, hipStream_t s) {
   const unsigned g = (unsigned)std::min<int64_t>(p.ntot * KB / kBlock, 4096);
   switch (lpa) {
-    case 1: hipLaunchKernelGGL((k_build<R, 1>), dim3(g), dim3(kBlock), 0, s, p, b, cond); break;
-    case 2: hipLaunchKernelGGL((k_build<R, 2>), dim3(g), dim3(kBlock), 0, s, p, b, cond); break;
-    case 4: hipLaunchKernelGGL((k_build<R, 4>), dim3(g), dim3(kBlock), 0, s, p, b, cond); break;
-    case 8: hipLaunchKernelGGL((k_build<R, 8>), dim3(g), dim3(kBlock), 0, s, p, b, cond); break;
-    default: hipLaunchKernelGGL((k_build<R, 16>), dim3(g), dim3(kBlock), 0, s, p, b, cond); break;
+    case 1: hipLaunchKernelGGL((k_build<R, 1, L16>), dim3(g), dim3(kBlock), 0, s, p, b, cond); break;
+    case 2: hipLaunchKernelGGL((k_build<R, 2, L16>), dim3(g), dim3(kBlock), 0, s, p, b, cond); break;
+    case 4: hipLaunchKernelGGL((k_build<R, 4, L16>), dim3(g), dim3(kBlock), 0, s, p, b, cond); break;
+    case 8: hipLaunchKernelGGL((k_build<R, 8, L16>), dim3(g), dim3(kBlock), 0, s, p, b, cond); break;
+    default: hipLaunchKernelGGL((k_build<R, 16, L16>), dim3(g), dim3(kBlock), 0, s, p, b, cond); break;
   }
 }
 
 void launch_build(const Params &p, const Buffers &b, int precision, int lpa, hipStream_t s, int32_t cond) {
-  if (precision) build_lpa<float>(p, b, lpa, cond, s);
-  else build_lpa<double>(p, b, lpa, cond, s);
+  if (precision) (p.list16 ? build_lpa<float, true> : build_lpa<float, false>)(p, b, lpa, cond, s);
+  else (p.list16 ? build_lpa<double, true> : build_lpa<double, false>)(p, b, lpa, cond, s);
 }
 
 void launch_density(const Params &p, const Buffers &b, int precision, int lpa, int32_t k, hipStream_t s) {
   switch (pot_form(p) + 3 * (precision ? 1 : 0)) {
-    case 0: density_lpa<double, 0>(p, b, lpa, k, s); break;
-    case 1: density_lpa<double, 1>(p, b, lpa, k, s); break;
-    case 2: density_lpa<double, 2>(p, b, lpa, k, s); break;
-    case 3: density_lpa<float, 0>(p, b, lpa, k, s); break;
-    case 4: density_lpa<float, 1>(p, b, lpa, k, s); break;
-    default: density_lpa<float, 2>(p, b, lpa, k, s); break;
+    case 0: (p.list16 ? density_lpa<double, 0, true> : density_lpa<double, 0, false>)(p, b, lpa, k, s); break;
+    case 1: (p.list16 ? density_lpa<double, 1, true> : density_lpa<double, 1, false>)(p, b, lpa, k, s); break;
+    case 2: (p.list16 ? density_lpa<double, 2, true> : density_lpa<double, 2, false>)(p, b, lpa, k, s); break;
+    case 3: (p.list16 ? density_lpa<float, 0, true> : density_lpa<float, 0, false>)(p, b, lpa, k, s); break;
+    case 4: (p.list16 ? density_lpa<float, 1, true> : density_lpa<float, 1, false>)(p, b, lpa, k, s); break;
+    default: (p.list16 ? density_lpa<float, 2, true> : density_lpa<float, 2, false>)(p, b, lpa, k, s); break;
   }
 }
 
 void launch_force(const Params &p, const Buffers &b, int precision, int lpa, int32_t k, int32_t mode,
                   hipStream_t s) {
   switch (pot_form(p) + 3 * (precision ? 1 : 0)) {
-    case 0: force_lpa<double, 0>(p, b, lpa, k, mode, s); break;
-    case 1: force_lpa<double, 1>(p, b, lpa, k, mode, s); break;
-    case 2: force_lpa<double, 2>(p, b, lpa, k, mode, s); break;
-    case 3: force_lpa<float, 0>(p, b, lpa, k, mode, s); break;
-    case 4: force_lpa<float, 1>(p, b, lpa, k, mode, s); break;
-    default: force_lpa<float, 2>(p, b, lpa, k, mode, s); break;
+    case 0: (p.list16 ? force_lpa<double, 0, true> : force_lpa<double, 0, false>)(p, b, lpa, k, mode, s); break;
+    case 1: (p.list16 ? force_lpa<double, 1, true> : force_lpa<double, 1, false>)(p, b, lpa, k, mode, s); break;
+    case 2: (p.list16 ? force_lpa<double, 2, true> : force_lpa<double, 2, false>)(p, b, lpa, k, mode, s); break;
+    case 3: (p.list16 ? force_lpa<float, 0, true> : force_lpa<float, 0, false>)(p, b, lpa, k, mode, s); break;
+    case 4: (p.list16 ? force_lpa<float, 1, true> : force_lpa<float, 1, false>)(p, b, lpa, k, mode, s); break;
+    default: (p.list16 ? force_lpa<float, 2, true> : force_lpa<float, 2, false>)(p, b, lpa, k, mode, s); break;
   }
 }
 

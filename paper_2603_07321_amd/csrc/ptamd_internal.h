@@ -34,7 +34,8 @@ enum : int {
   E_OVERFLOW = 4,  // Verlet list capacity exceeded
   E_DRIFT = 8,     // an atom drifted beyond the binning margin before a list build
   E_STATE = 16,    // thermostat: T <= 0 or lambda^2 < 0
-  E_SKIN = 32      // an atom moved more than half the skin since the list build (a trigger was missed)
+  E_SKIN = 32,     // an atom moved more than half the skin since the list build (a trigger was missed)
+  E_WIDE = 64      // a list entry's offset does not fit the 16-bit list form
 };
 
 // Device-resident control block (one per system).
@@ -125,19 +126,20 @@ struct Params {
   double tab_inv_drho; // 1 / drho
   int32_t tab_nrho;
   int32_t fold;        // nonzero (mixed form): the density pass does the step's kick-drift (Buffers::pnext)
+  int32_t list16;      // nonzero: the Verlet lists hold 16-bit offsets (nbr16_index), else 32-bit indices
 };
 
 // Device buffers (pointers), passed by value.
 struct Buffers {
   double *x, *y, *z, *vx, *vy, *vz, *fx, *fy, *fz;
   void *pos4;          // float4 or double4: x, y, z, B'
-  void *pnext;         // mixed form: float4 x + dt (v + dt F / 2m), the position after the next step at lambda = 1
+  void *pnext;         // mixed form: float4 x + dt (lp v + dt F / 2m), the position after the next step (lp: the last lambda)
   uint8_t *group;
   int32_t *orig;       // original global index of each sorted atom
   int32_t *cell;       // linear cell index (within the replica grid) at the last sort
   float *xs, *ys, *zs; // positions at the last sort
   float *xr, *yr, *zr; // positions at the last list build
-  int32_t *nbr;        // Verlet lists, [slot][atom*lpa + lane]
+  int32_t *nbr;        // Verlet lists, [slot][atom*lpa + lane] (32-bit indices or 16-bit offsets, Params::list16)
   int32_t *ncount;     // list length per atom
   int32_t *cell_start; // global cell arrays: [cell_off + c]
   int32_t *cell_count;
@@ -167,6 +169,19 @@ constexpr int kPass = 2 * kGroup;
 __host__ __device__ inline size_t nbr_index(int64_t i, int e, int lpa, int64_t stride) {
   const int l = e % lpa, s = e / lpa;
   return ((size_t)(s / kGroup) * (size_t)stride + (size_t)i * lpa + l) * kGroup + (s % kGroup);
+}
+
+// The 16-bit form of the lists: entry e of atom i holds the offset j - i
+// (sorted order keeps an atom's neighbours within a few bin layers of it),
+// eight to a group per lane, so one 16-byte load gives a lane a whole pass
+// and the pair kernels read half the list bytes.  kOffSentinel stands for
+// the sentinel index ntot.  A system whose offsets outgrow 16 bits (a build
+// meets one: E_WIDE) switches to the 32-bit form for good.
+constexpr int kGroup16 = 8;
+constexpr int kOffSentinel = -32768;
+__host__ __device__ inline size_t nbr16_index(int64_t i, int e, int lpa, int64_t stride) {
+  const int l = e % lpa, s = e / lpa;
+  return ((size_t)(s / kGroup16) * (size_t)stride + (size_t)i * lpa + l) * kGroup16 + (s % kGroup16);
 }
 
 // ---- launch wrappers (kernels.hip) ----

@@ -254,7 +254,8 @@ static void alloc_list(ptamd_system *s, int cap) {
   cap = (cap + q - 1) / q * q;
   dfree(s->B.nbr);
   s->B.nbr = nullptr;
-  s->B.nbr = dalloc<int32_t>((size_t)s->ntot * cap);
+  // 16-bit form: two entries per 32-bit word
+  s->B.nbr = dalloc<int32_t>((size_t)s->ntot * cap / (s->P.list16 ? 2 : 1));
   s->cap = cap;
   s->P.cap_slots = cap / s->lpa;
   invalidate_graphs(s);
@@ -380,10 +381,12 @@ static ptamd_system *create_from_hosts(const std::vector<HostState> &hs, const s
     // The mixed form folds each step's kick-drift into its density pass when
     // the system is small: the fold saves a kernel boundary (~2 us) per step
     // but adds work per atom and per block (the force pass writes the next
-    // positions, every density block takes lambda itself).  Measured: 62,500
-    // atoms +4%; 500,000 atoms -17%, 64 x 13,500 atoms -6%, 725,000 atoms in
-    // 16 cubes -12%.
+    // positions, the density pass holds the atom's state through its pair
+    // loop, each replica's first block records the sample between its pair
+    // loop and its update).  Measured: 62,500 atoms +15%, 131,072 atoms +2%;
+    // 256,000 atoms -1%, 500,000 atoms -4%, 64 x 13,500 atoms -7%.
     P.fold = (s->precision && s->ntot <= kFoldMaxAtoms) ? 1 : 0;
+    P.list16 = 1;  // until a build meets an offset beyond 16 bits
 
     Buffers &B = s->B;
     alloc_buffers(B, s->ntot, s->precision, true);
@@ -698,9 +701,11 @@ static void initial_forces(ptamd_system *s) {
   read_ctl(s);
   s->list_builds++;
   s->need_build = false;
-  if (s->h_ctl->err & E_OVERFLOW) {
-    // grow the lists and try again from the same positions
-    alloc_list(s, s->cap * 3 / 2);
+  if (s->h_ctl->err & (E_OVERFLOW | E_WIDE)) {
+    // grow the lists, or widen them to 32-bit indices, and try again from
+    // the same positions
+    if (s->h_ctl->err & E_WIDE) s->P.list16 = 0;
+    alloc_list(s, (s->h_ctl->err & E_OVERFLOW) ? s->cap * 3 / 2 : s->cap);
     clear_err(s);
     s->need_sort = true;
     return initial_forces(s);
@@ -821,11 +826,12 @@ static void run_burst(ptamd_system *s, int64_t n_steps, ptamd_averages *out, con
     s->list_builds += s->h_ctl->nbuild - s->nbuild_seen;
     s->nbuild_seen = s->h_ctl->nbuild;
     const int err = s->h_ctl->err;
-    if (err & (E_DRIFT | E_OVERFLOW | E_SKIN)) {
+    if (err & (E_DRIFT | E_OVERFLOW | E_SKIN | E_WIDE)) {
       // a bound the lists rely on did not hold: re-run the chunk from its start
       snapshot(s, true);
       s->stats_valid = false;
-      if (err & E_OVERFLOW) alloc_list(s, s->cap * 3 / 2);
+      if (err & E_WIDE) s->P.list16 = 0;
+      if (err & (E_OVERFLOW | E_WIDE)) alloc_list(s, (err & E_OVERFLOW) ? s->cap * 3 / 2 : s->cap);
       clear_err(s);
       s->need_sort = true;
       s->rollbacks++;
@@ -1130,17 +1136,25 @@ static void get_neighbors(ptamd_system *s, int64_t *offsets, int32_t *idx, int64
   initial_forces(s);  // sorts, rebuilds the lists at the current positions
   const int64_t N = s->ntot;
   std::vector<int32_t> o(N), cnt(N);
-  std::vector<int32_t> nb((size_t)N * s->cap);
+  const bool l16 = s->P.list16 != 0;
+  std::vector<int32_t> nb((size_t)N * s->cap / (l16 ? 2 : 1));
   d2h(s, o.data(), s->B.orig, 4 * N);
   d2h(s, cnt.data(), s->B.ncount, 4 * N);
-  d2h(s, nb.data(), s->B.nbr, (size_t)4 * N * s->cap);
+  d2h(s, nb.data(), s->B.nbr, nb.size() * 4);
+  const int16_t *nb16 = reinterpret_cast<const int16_t *>(nb.data());
   std::vector<std::vector<int32_t>> rows(s->nreal);
   for (int64_t i = 0; i < N; ++i) {
     if (o[i] < 0) continue;
     auto &row = rows[o[i]];
     row.reserve(cnt[i]);
     for (int e = 0; e < cnt[i]; ++e) {
-      const int32_t j = nb[nbr_index(i, e, s->lpa, s->P.nbr_stride)];
+      int32_t j;
+      if (l16) {
+        const int w = nb16[nbr16_index(i, e, s->lpa, s->P.nbr_stride)];
+        j = w == kOffSentinel ? (int32_t)N : (int32_t)(i + w);
+      } else {
+        j = nb[nbr_index(i, e, s->lpa, s->P.nbr_stride)];
+      }
       row.push_back(o[j]);
     }
     std::sort(row.begin(), row.end());
@@ -1622,6 +1636,8 @@ ptamd_status ptamd_get_info(const ptamd_system *sys, ptamd_info *info) {
     info->steps = sys->steps_total;
     info->skin = sys->skin;
     info->bin_margin = sys->margin;
+    info->list_index_bits = sys->P.list16 ? 16 : 32;
+    info->folded = sys->P.fold;
   });
 }
 

@@ -31,6 +31,19 @@ def fcc_points(nc: int, a: float = A_AL):
     return xyz[:, 0].copy(), xyz[:, 1].copy(), xyz[:, 2].copy(), p.astype(np.int32)
 
 
+def fcc_slab(nx: int, ny: int, nz: int, noise: float, seed: int, a: float = A_AL):
+    """Perturbed FCC block of nx x ny x nz cells, every atom mobile, at rest
+    (a thin film when nz is small)."""
+    basis = np.array([[0, 0, 0], [1, 1, 0], [1, 0, 1], [0, 1, 1]], dtype=np.int64)
+    iz, iy, ix = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    cells = np.stack([ix.ravel(), iy.ravel(), iz.ravel()], axis=1)
+    p = (2 * cells[:, None, :] + basis[None, :, :]).reshape(-1, 3).astype(np.float64) * (0.5 * a)
+    x, y, z = perturb(p[:, 0], p[:, 1], p[:, 2], noise, seed)
+    zero = np.zeros(len(x))
+    return dict(x=x, y=y, z=z, vx=zero.copy(), vy=zero.copy(), vz=zero.copy(), group=np.zeros(len(x), np.uint8),
+                volume0=nx * ny * nz * a ** 3, area0=nx * ny * a ** 2)
+
+
 def slab_groups(pz: np.ndarray, nc: int, fix_slabs: bool = True) -> np.ndarray:
     """Tags: 0 mobile, 1 bottom three z planes, 2 top three z planes."""
     g = np.zeros(len(pz), np.uint8)
