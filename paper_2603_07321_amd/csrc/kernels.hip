@@ -739,6 +739,7 @@ __global__ __launch_bounds__(kBlock) void k_pos4(Params p, Buffers b) {
 // prefix, so the order is fixed: rows in stencil order, atoms in sorted order.
 constexpr int KB = 16;   // lanes per atom in the list build
 constexpr int KCH = 4;   // candidates per lane per pass, loaded before use
+constexpr int NRL = (25 + KB - 1) / KB;  // stencil rows per lane in phase 1
 
 __device__ __forceinline__ double box_dist(double v, double o, double h, int n, int dim) {
   const double lo = (n == 0) ? -1e300 : o + n * h;
@@ -766,10 +767,11 @@ __device__ void build_one(const Params &p, const Buffers &b, int64_t i, int lane
   const double hb = p.bin_h;
   const int cl = b.cell[i];
   const int cx = cl % dxn, cy = (cl / dxn) % dyn, cz = cl / (dxn * dyn);
-  // phase 1: lane l resolves stencil rows l and l + 16 into atom ranges
-  int rs[2] = {0, 0}, re[2] = {0, 0};
+  // phase 1: lane l resolves stencil rows l, l + KB, ... into atom ranges
+  int rs[NRL], re[NRL];
 #pragma unroll
-  for (int h2 = 0; h2 < 2; ++h2) {
+  for (int h2 = 0; h2 < NRL; ++h2) {
+    rs[h2] = re[h2] = 0;
     const int q = lane + h2 * KB;
     if (q >= 25) continue;
     const int nz = cz + q / 5 - 2, ny = cy + q % 5 - 2;
@@ -809,8 +811,15 @@ __device__ void build_one(const Params &p, const Buffers &b, int64_t i, int lane
   int cnt = 0;
   for (int q = 0; q < 25; ++q) {
     const int src = gbase + (q % KB);
-    const int s0 = __shfl(q < KB ? rs[0] : rs[1], src);
-    const int e0 = __shfl(q < KB ? re[0] : re[1], src);
+    int rq = rs[0], eq = re[0];
+#pragma unroll
+    for (int h2 = 1; h2 < NRL; ++h2)
+      if (q >= h2 * KB) {
+        rq = rs[h2];
+        eq = re[h2];
+      }
+    const int s0 = __shfl(rq, src);
+    const int e0 = __shfl(eq, src);
     for (int t = s0; t < e0; t += KB * KCH) {
       int jc[KCH];
       float4 qv[KCH];
