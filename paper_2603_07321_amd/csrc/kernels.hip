@@ -1312,62 +1312,120 @@ __global__ __launch_bounds__(kBlock) void k_assign_count(Params p, Buffers b, in
   }
 }
 
-// exclusive scan of one replica's cell counts (one block per replica)
-__global__ __launch_bounds__(1024) void k_scan_cells(Params p, Buffers b, int32_t *cursor) {
-  const int r = blockIdx.x;
-  const RepInfo &rp = b.rep[r];
-  const int64_t nc = rp.ncells;
-  const int32_t *cnt = b.cell_count + rp.cell_off;
-  int32_t *st = b.cell_start + rp.cell_off;
-  int32_t *cur = cursor + rp.cell_off;
-  // per-thread chunk sums, then an exclusive scan over the 1024 threads:
-  // inclusive scans within each wavefront (shuffles), then over the 16
-  // wavefront totals.  Counts stay below 2^27, so 32-bit sums suffice.
-  __shared__ int wsum[16];
-  const int64_t per = (nc + 1023) / 1024;
-  const int64_t lo = threadIdx.x * per, hi = min(nc, lo + per);
-  int s = 0;
-  // chunks of 16 independent loads: a thread's cells cost a few load
-  // latencies, not one per cell
-  for (int64_t c0 = lo; c0 < hi; c0 += 16) {
-    int v[16];
+// Exclusive scan of each replica's cell counts into cell_start (and the
+// scatter cursors), starting at the replica's first sorted atom.  Three
+// launches over tiles of kScanTile cells (grid: tiles x replicas, blocks
+// past a replica's last tile leave at once): the tile sums; their scan per
+// replica; each tile's scan from its base.  Every wavefront reads and
+// writes contiguous runs.  (A single block per replica, each thread a run
+// of its own, took 136 us on a 97,000-cell grid: its lanes read 64
+// different cache lines per load through one compute unit.)  Counts stay
+// below 2^27, so 32-bit sums suffice.
+constexpr int kScanPer = 16;                    // cells per thread in a tile
+constexpr int kScanTile = kBlock * kScanPer;    // 4096
+
+// Sum over the block (all kBlock threads), returned to every thread.
+__device__ __forceinline__ int block_sum_int(int v) {
+  __shared__ int ws[kBlock / 64];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) v[u] = (c0 + u < hi) ? cnt[c0 + u] : 0;
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = v;
+  __syncthreads();
+  int t = 0;
 #pragma unroll
-    for (int u = 0; u < 16; ++u) s += v[u];
+  for (int w = 0; w < kBlock / 64; ++w) t += ws[w];
+  return t;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_tiles(Buffers b, int32_t *tsum, int32_t tmax) {
+  const int r = blockIdx.y;
+  const int64_t ncl = b.rep[r].ncells;
+  const int64_t c0 = (int64_t)blockIdx.x * kScanTile;
+  if (c0 >= ncl) return;  // uniform over the block
+  const int32_t *cnt = b.cell_count + b.rep[r].cell_off + c0;
+  const int n = (int)min<int64_t>(kScanTile, ncl - c0);
+  int v[kScanPer];
+#pragma unroll
+  for (int u = 0; u < kScanPer; ++u) {
+    const int k = u * kBlock + (int)threadIdx.x;  // contiguous over the block
+    v[u] = k < n ? cnt[k] : 0;
   }
+  int sum = 0;
+#pragma unroll
+  for (int u = 0; u < kScanPer; ++u) sum += v[u];
+  sum = block_sum_int(sum);
+  if (threadIdx.x == 0) tsum[(size_t)r * tmax + blockIdx.x] = sum;
+}
+
+// one block per replica: tile sums -> tile bases (the replica's first atom
+// plus the sums of the tiles before), in place
+__global__ __launch_bounds__(kBlock) void k_scan_tile_sums(Buffers b, int32_t *tsum, int32_t tmax) {
+  __shared__ int ws[kBlock / 64];
+  const int r = blockIdx.x;
+  const int nt = (int)((b.rep[r].ncells + kScanTile - 1) / kScanTile);
+  int32_t *t = tsum + (size_t)r * tmax;
+  int carry = (int)b.rep[r].abeg;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  int v = s;
+  for (int k0 = 0; k0 < nt; k0 += kBlock) {
+    const int k = k0 + (int)threadIdx.x;
+    const int x = k < nt ? t[k] : 0;
+    int v = x;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(v, o);
+      if (lane >= o) v += y;
+    }
+    if (lane == 63) ws[wid] = v;
+    __syncthreads();
+    int before = 0, all = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) {
+      before += w < wid ? ws[w] : 0;
+      all += ws[w];
+    }
+    if (k < nt) t[k] = carry + before + v - x;
+    carry += all;
+    __syncthreads();  // ws is rewritten by the next round
+  }
+}
+
+// each tile's exclusive scan from its base: thread t takes cells
+// [t kScanPer, (t + 1) kScanPer) of the tile
+__global__ __launch_bounds__(kBlock) void k_scan_write(Buffers b, const int32_t *tbase, int32_t tmax,
+                                                       int32_t *cursor) {
+  __shared__ int ws[kBlock / 64];
+  const int r = blockIdx.y;
+  const int64_t ncl = b.rep[r].ncells;
+  const int64_t c0 = (int64_t)blockIdx.x * kScanTile;
+  if (c0 >= ncl) return;  // uniform over the block
+  const int64_t off = b.rep[r].cell_off + c0;
+  const int n = (int)min<int64_t>(kScanTile, ncl - c0);
+  const int k0 = (int)threadIdx.x * kScanPer;
+  int v[kScanPer];
+#pragma unroll
+  for (int u = 0; u < kScanPer; ++u) v[u] = k0 + u < n ? b.cell_count[off + k0 + u] : 0;
+  int sum = 0;
+#pragma unroll
+  for (int u = 0; u < kScanPer; ++u) sum += v[u];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int incl = sum;
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
-    const int t = __shfl_up(v, o);
-    if (lane >= o) v += t;
+    const int y = __shfl_up(incl, o);
+    if (lane >= o) incl += y;
   }
-  if (lane == 63) wsum[wid] = v;
+  if (lane == 63) ws[wid] = incl;
   __syncthreads();
-  if (wid == 0) {
-    int w = lane < 16 ? wsum[lane] : 0;
+  int run = tbase[(size_t)r * tmax + blockIdx.x] + incl - sum;
 #pragma unroll
-    for (int o = 1; o < 16; o <<= 1) {
-      const int t = __shfl_up(w, o);
-      if (lane >= o) w += t;
+  for (int w = 0; w < kBlock / 64; ++w) run += w < wid ? ws[w] : 0;
+#pragma unroll
+  for (int u = 0; u < kScanPer; ++u)
+    if (k0 + u < n) {
+      b.cell_start[off + k0 + u] = run;
+      cursor[off + k0 + u] = run;
+      run += v[u];
     }
-    if (lane < 16) wsum[lane] = w;
-  }
-  __syncthreads();
-  int64_t run = rp.abeg + (v - s) + (wid > 0 ? wsum[wid - 1] : 0);
-  for (int64_t c0 = lo; c0 < hi; c0 += 16) {
-    int w[16];
-#pragma unroll
-    for (int u = 0; u < 16; ++u) w[u] = (c0 + u < hi) ? cnt[c0 + u] : 0;
-#pragma unroll
-    for (int u = 0; u < 16; ++u)
-      if (c0 + u < hi) {
-        st[c0 + u] = (int32_t)run;
-        cur[c0 + u] = (int32_t)run;
-        run += w[u];
-      }
-  }
 }
 
 __global__ __launch_bounds__(kBlock) void k_scatter(Buffers b, const int32_t *key, int32_t *cursor, int32_t *tmp) {
@@ -1680,8 +1738,14 @@ void launch_assign_count(const Params &p, const Buffers &b, int32_t *key, hipStr
   hipLaunchKernelGGL(k_assign_count, dim3(tiles(p)), dim3(kBlock), 0, s, p, b, key);
 }
 
-void launch_scan_cells(const Params &p, const Buffers &b, int32_t *cursor, hipStream_t s) {
-  hipLaunchKernelGGL(k_scan_cells, dim3(p.n_rep), dim3(1024), 0, s, p, b, cursor);
+int scan_tiles(int64_t ncells) { return (int)((ncells + kScanTile - 1) / kScanTile); }
+
+void launch_scan_cells(const Params &p, const Buffers &b, int32_t *cursor, int32_t *tsum, int32_t tmax,
+                       hipStream_t s) {
+  const dim3 grid((unsigned)tmax, (unsigned)p.n_rep);
+  hipLaunchKernelGGL(k_scan_tiles, grid, dim3(kBlock), 0, s, b, tsum, tmax);
+  hipLaunchKernelGGL(k_scan_tile_sums, dim3(p.n_rep), dim3(kBlock), 0, s, b, tsum, tmax);
+  hipLaunchKernelGGL(k_scan_write, grid, dim3(kBlock), 0, s, b, tsum, tmax, cursor);
 }
 
 void launch_scatter(const Params &p, const Buffers &b, const int32_t *key, int32_t *cursor, int32_t *tmp,

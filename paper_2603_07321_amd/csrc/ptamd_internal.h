@@ -200,7 +200,11 @@ void launch_snapshot(const Buffers &b, double *snap, unsigned long long *snap_sl
                      int64_t ntot, int64_t nslots, int64_t nacc, hipStream_t s);
 void launch_copy_back(const Params &p, const Buffers &b, const Buffers &scratch, int precision, hipStream_t s);
 void launch_assign_count(const Params &p, const Buffers &b, int32_t *key, hipStream_t s);
-void launch_scan_cells(const Params &p, const Buffers &b, int32_t *cursor, hipStream_t s);
+// tiles of the cell scan for a replica of ncells cells; tsum holds tmax
+// (the largest tile count of any replica) entries per replica
+int scan_tiles(int64_t ncells);
+void launch_scan_cells(const Params &p, const Buffers &b, int32_t *cursor, int32_t *tsum, int32_t tmax,
+                       hipStream_t s);
 void launch_scatter(const Params &p, const Buffers &b, const int32_t *key, int32_t *cursor, int32_t *tmp,
                     hipStream_t s);
 void launch_cell_sort(const Params &p, const Buffers &b, const int32_t *tmp, int32_t *perm, int64_t ncells_tot,

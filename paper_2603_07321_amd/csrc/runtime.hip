@@ -94,6 +94,8 @@ struct ptamd_system {
   std::vector<int32_t> blk_rep_h;
   int32_t *d_key = nullptr, *d_cursor = nullptr, *d_tmp = nullptr, *d_perm = nullptr;
   int64_t cells_cap = 0;
+  int32_t *d_tiles = nullptr;  // tile sums of the cell scan
+  int64_t tiles_cap = 0;
   // snapshot for roll-back
   double *snap = nullptr;  // 12 arrays of ntot doubles
   bool msum_valid = false; // the position sums hold the samples of the last burst
@@ -462,7 +464,7 @@ static ptamd_system *create_from_hosts(const std::vector<HostState> &hs, const s
   } catch (...) {
     free_buffers(s->B);
     free_buffers(s->S);
-    dfree(s->d_key); dfree(s->d_tmp); dfree(s->d_perm); dfree(s->d_cursor);
+    dfree(s->d_key); dfree(s->d_tmp); dfree(s->d_perm); dfree(s->d_cursor); dfree(s->d_tiles);
     dfree(s->snap); dfree(s->snap_slots); dfree(s->snap_acc);
     if (s->h_stat) (void)hipHostFree(s->h_stat);
     if (s->h_rep) (void)hipHostFree(s->h_rep);
@@ -548,10 +550,19 @@ static void sort_system(ptamd_system *s) {
     s->cells_cap = capc;
     invalidate_graphs(s);
   }
+  int tmax = 1;
+  for (int r = 0; r < s->n_rep; ++r) tmax = std::max(tmax, scan_tiles(s->reps[r].ncells));
+  if ((int64_t)tmax * s->n_rep > s->tiles_cap) {
+    sync(s);
+    dfree(s->d_tiles);
+    s->d_tiles = nullptr;
+    s->tiles_cap = (int64_t)tmax * s->n_rep * 2;
+    s->d_tiles = dalloc<int32_t>(s->tiles_cap);
+  }
   upload_reps(s);
   launch_fill_i64(reinterpret_cast<unsigned long long *>(B.cell_count), (cells + 1) / 2, 0ull, s->stream);
   launch_assign_count(s->P, B, s->d_key, s->stream);
-  launch_scan_cells(s->P, B, s->d_cursor, s->stream);
+  launch_scan_cells(s->P, B, s->d_cursor, s->d_tiles, tmax, s->stream);
   launch_scatter(s->P, B, s->d_key, s->d_cursor, s->d_tmp, s->stream);
   launch_cell_sort(s->P, B, s->d_tmp, s->d_perm, cells, s->stream);
   launch_permute(s->P, B, s->S, s->d_perm, s->d_key, s->precision, s->stream);
@@ -1353,7 +1364,7 @@ static void destroy(ptamd_system *s) {
   invalidate_graphs(s);
   free_buffers(s->B);
   free_buffers(s->S);
-  dfree(s->d_key); dfree(s->d_tmp); dfree(s->d_perm); dfree(s->d_cursor);
+  dfree(s->d_key); dfree(s->d_tmp); dfree(s->d_perm); dfree(s->d_cursor); dfree(s->d_tiles);
   dfree(s->snap); dfree(s->snap_slots); dfree(s->snap_acc);
   if (s->h_stat) (void)hipHostFree(s->h_stat);
   if (s->h_rep) (void)hipHostFree(s->h_rep);
