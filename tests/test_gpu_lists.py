@@ -6,8 +6,10 @@ on it.  A system whose offsets outgrow 16 bits switches to 32-bit indices
 at the list build that meets one.  Here a film 20 A thick, whose sorted
 order puts ~27,000 atoms in each of its three layers of bins (an atom of
 the first layer has neighbours up to ~58,000 places on), forces that switch; its forces and
-neighbour sets are checked against the oracle on sampled atoms (bars as in
-the parity tests: FP64 forces 1e-9 of max(|F|, F_rms), mixed 1e-4).
+neighbour sets are checked against the oracle on sampled atoms (forces
+relative to max(|F|, F_rms): FP64 1e-9; mixed 2e-4, the parity tests' bar,
+where coordinates up to 260 A put the FP32 rounding of positions at
+1.5e-5 A; measured 8e-5).
 """
 import numpy as np
 import pytest
@@ -68,7 +70,7 @@ def test_wide_offsets_switch_to_32bit_indices(film, precision):
     frms = np.sqrt((ref ** 2).sum(1).mean())
     err = (np.linalg.norm(F[sample] - ref, axis=1) / np.maximum(np.linalg.norm(ref, axis=1), frms)).max()
     print(f"sampled forces: {err:.2e}")
-    assert err <= (1e-9 if precision == 0 else 1e-4)
+    assert err <= (1e-9 if precision == 0 else 2e-4)
     rl = p.rc + info["skin"]
     for i in sample[:16]:
         d2 = (s["x"] - s["x"][i]) ** 2 + (s["y"] - s["y"][i]) ** 2 + (s["z"] - s["z"][i]) ** 2
@@ -76,3 +78,46 @@ def test_wide_offsets_switch_to_32bit_indices(film, precision):
         want = want[want != i]
         assert np.array_equal(idx[off[i]:off[i + 1]], want), i
     assert np.isfinite(a["pe"]) and a["n_samples"] == 20
+
+
+
+def test_neighbours_of_a_batch():
+    """Three replicas: the cell scan restarts at each replica's first atom.
+    Every list (16-bit form) matches the oracle's neighbour sets, replica by
+    replica."""
+    O = _orc()
+    descs = [P.lattice_desc(8, 300.0, 21), P.lattice_desc(5, 300.0, 22), P.lattice_desc(7, 300.0, 23)]
+    with P.System.batch(descs, md=P.md_params(precision=1, lanes_per_atom=4)) as b:
+        b.run_fast_md(30)
+        st = b.get_state()
+        off, idx = b.get_neighbors()
+        info = b.info()
+    assert info["list_index_bits"] == 16
+    a0 = 0
+    for d in descs:
+        n = 4 * d.n_cells ** 3
+        roff, ridx = O.neighbors(st["x"][a0:a0 + n], st["y"][a0:a0 + n], st["z"][a0:a0 + n], 8.1 + info["skin"])
+        assert np.array_equal(off[a0:a0 + n + 1] - off[a0], roff)
+        assert np.array_equal(idx[off[a0]:off[a0 + n]], ridx + a0)
+        a0 += n
+
+
+def test_neighbours_over_several_scan_tiles():
+    """A loose simple-cubic arrangement (8,000 atoms 6 A apart, 114 A across):
+    its grid has ~5,800 bins, so the cell scan spans two 4,096-bin tiles.
+    The lists match the oracle's neighbour sets."""
+    O = _orc()
+    x, y, z = synth.gas(20, 6.0, 31, jitter=0.3)
+    n = len(x)
+    zero = np.zeros(n)
+    s = dict(x=x, y=y, z=z, vx=zero, vy=zero.copy(), vz=zero.copy(), group=np.zeros(n, np.uint8),
+             volume0=114.0 ** 3, area0=114.0 ** 2)
+    with P.System.from_state(s, T0=300.0, md=P.md_params(precision=1, lanes_per_atom=4, thermostat=0)) as g:
+        off, idx = g.get_neighbors()
+        cxyz, origin, inv_h, dims = g.get_cells()
+        info = g.info()
+    print(f"\ngrid {dims[0]}: {int(np.prod(dims[0]))} bins")
+    assert int(np.prod(dims[0])) > 4096
+    roff, ridx = O.neighbors(x, y, z, 8.1 + info["skin"])
+    assert np.array_equal(off, roff)
+    assert np.array_equal(idx, ridx)
