@@ -8,6 +8,11 @@ example ``PTAMD_ENODEV`` without a gfx950 GPU.
 
 Module-level functions carry the names of the C entry points without the
 ``ptamd_`` prefix; :class:`System` wraps a handle for convenience.
+
+In a process that also uses PyTorch on the GPU (to share a stream with
+:meth:`System.set_stream`, say), import torch before this package: torch
+ships its own copy of the HIP runtime, and when this library's runtime was
+loaded first, the library later saw no device (``PTAMD_ENODEV``).
 """
 from __future__ import annotations
 
