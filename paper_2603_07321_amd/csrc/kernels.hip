@@ -989,7 +989,11 @@ __global__ __launch_bounds__(kBlock) void k_density(Params p, Buffers b, int32_t
   long long q[1] = {0};
   if (lane == 0 && real) {
     double rb = (double)acc;
-    if (NM != 2) rb += -(double)np * p.rhoc - p.drhoc * ((double)sr - (double)np * p.rc);
+    if (NM != 2) {
+      rb += -(double)np * p.rhoc - p.drhoc * ((double)sr - (double)np * p.rc);
+      // the same pairs shift the pair energy, which the force pass adds
+      b.eshift[i] = -(double)np * p.Vc - p.dVc * ((double)sr - (double)np * p.rc);
+    }
     double Bp = 0.0, B = 0.0;
     if (NM == 2) {
       tab_embed(p, b.tab_F, rb, &B, &Bp);
@@ -1045,13 +1049,14 @@ __global__ __launch_bounds__(kBlock) void k_force(Params p, Buffers b, int32_t k
     x = b.x[i]; y = b.y[i]; z = b.z[i];
     vx = b.vx[i]; vy = b.vy[i]; vz = b.vz[i];
   }
+  const double eshift = (NM != 2 && real && lane == 0) ? b.eshift[i] : 0.0;  // read ahead too
   const V4 *p4 = reinterpret_cast<const V4 *>(b.pos4);
   // Sutton-Chen, with w_j = -m B'_j from the density pass:
   //   dU/dr = [-n eps (a/r)^n + (w_i + w_j) (a/r)^m] / r - (dVc - (w_i + w_j) drhoc / m)
-  // and the pair energy V - Vc - (r - rc) dVc summed as sum(-n V), sum(r)
-  // and the pair count, shifted once per atom.  Tables: B' as is.
-  R fx = 0, fy = 0, fz = 0, ep = 0, w = 0, sr = 0;
-  int np = 0;
+  // and the pair energy V - Vc - (r - rc) dVc summed as sum(-n V) here and
+  // the shift, which the density pass formed from its sums of r and of the
+  // pairs.  Tables: B' as is.
+  R fx = 0, fy = 0, fz = 0, ep = 0, w = 0;
   if (real) {
     const V4 pi = p4[i];
     const R rc2 = (R)p.rc2, a = (R)p.a;
@@ -1091,8 +1096,6 @@ __global__ __launch_bounds__(kBlock) void k_force(Params p, Buffers b, int32_t k
             const R D = dVc - ws * dm;
             f = (C * rinv - D) * rinv;
             ep += A;
-            sr += r2 * rinv;
-            ++np;
           }
           fx += f * dx;
           fy += f * dy;
@@ -1109,10 +1112,6 @@ __global__ __launch_bounds__(kBlock) void k_force(Params p, Buffers b, int32_t k
     fz += __shfl_xor(fz, o);
     ep += __shfl_xor(ep, o);
     w += __shfl_xor(w, o);
-    if (NM != 2) {
-      sr += __shfl_xor(sr, o);
-      np += __shfl_xor(np, o);
-    }
   }
   long long q[kNQ] = {0, 0, 0, 0, 0, 0, 0, 0};
   if (lane == 0 && real) {
@@ -1153,9 +1152,8 @@ __global__ __launch_bounds__(kBlock) void k_force(Params p, Buffers b, int32_t k
           atomicOr(&b.ctl->rebuild, 1);
       }
     }
-    // pair energy of the atom: tables sum V; Sutton-Chen sums -n V, r and the count
-    const double epair = (NM == 2) ? (double)ep
-                                   : -(double)ep / p.n - (double)np * p.Vc - p.dVc * ((double)sr - (double)np * p.rc);
+    // pair energy of the atom: tables sum V; Sutton-Chen sums -n V, plus the shift
+    const double epair = (NM == 2) ? (double)ep : -(double)ep / p.n + eshift;
     q[Q_EPAIR] = to_fix(0.5 * epair);
     q[Q_WZZ] = to_fix(-0.5 * (double)w);
     if (g == 2) q[Q_RZ] = to_fix(-Fz);

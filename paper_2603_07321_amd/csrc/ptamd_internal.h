@@ -141,6 +141,8 @@ struct Buffers {
   float *xr, *yr, *zr; // positions at the last list build
   int32_t *nbr;        // Verlet lists, [slot][atom*lpa + lane] (32-bit indices or 16-bit offsets, Params::list16)
   int32_t *ncount;     // list length per atom
+  double *eshift;      // Sutton-Chen: the pair-energy shift -n_c Vc - dVc (sum r - n_c rc) over the atom's
+                       // pairs within rc, from the density pass (which sums r and n_c for rho's shift)
   int32_t *cell_start; // global cell arrays: [cell_off + c]
   int32_t *cell_count;
   int32_t *blk_rep;    // replica of each tile

@@ -211,13 +211,14 @@ static void alloc_buffers(Buffers &b, int64_t ntot, int precision, bool primary)
   if (primary) {
     b.xr = dalloc<float>(ntot); b.yr = dalloc<float>(ntot); b.zr = dalloc<float>(ntot);
     b.ncount = dalloc<int32_t>(ntot);
+    b.eshift = dalloc<double>(ntot);
     if (precision && ntot <= kFoldMaxAtoms) b.pnext = dalloc<float4>(ntot + 1);  // with the sentinel, as pos4
   }
 }
 
 static void free_buffers(Buffers &b) {
   void *ptrs[] = {b.x, b.y, b.z, b.vx, b.vy, b.vz, b.fx, b.fy, b.fz, b.pos4, b.pnext, b.group, b.orig, b.cell,
-                  b.xs, b.ys, b.zs, b.xr, b.yr, b.zr, b.nbr, b.ncount, b.cell_start, b.cell_count,
+                  b.xs, b.ys, b.zs, b.xr, b.yr, b.zr, b.nbr, b.ncount, b.eshift, b.cell_start, b.cell_count,
                   b.blk_rep, b.rep, b.acc, b.slots, b.stat, b.series, b.ktime, b.msx, b.msy, b.msz,
                   b.tab_r, b.tab_F};
   for (void *p : ptrs) dfree(p);
