@@ -893,11 +893,12 @@ __global__ __launch_bounds__(kBlock) void k_build(Params p, Buffers b, int32_t c
 // pair loop takes every position, the atom's own included, from
 // Buffers::pnext, which the previous force pass wrote (the position after
 // this step's drift, with the last lambda taken for this step's), so it
-// needs neither lambda nor any other atom's update and starts at once.  After it, every block takes
-// lambda from the slot sums (the replica's first block also records the
-// sample) and each atom's lanes update it exactly (lane 0 stores, the gather
-// copy with its B').  One kernel boundary less per step.  Step 0 (forces
-// at a burst's start) is the plain density pass.
+// needs neither lambda nor any other atom's update and starts at once.
+// After it, every block takes lambda from the slot sums (start_lambda: the
+// replica's first block also records the sample) and each atom's lanes
+// update it exactly (lane 0 stores, the gather copy with its B').  One
+// kernel boundary less per step.  Step 0 (forces at a burst's start) is
+// the plain density pass.
 template <class R, int LPA, int NM, bool L16>
 __global__ __launch_bounds__(kBlock) void k_density(Params p, Buffers b, int32_t k) {
   using V4 = typename V4T<R>::T;
