@@ -131,6 +131,8 @@ def main() -> int:
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 side measurement")
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-device-probe", action="store_true",
+                    help="skip the achievable copy and FMA rates measured after the timed region")
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="before the timed region, copy this many MiB device-to-device (a known-size kernel "
@@ -173,6 +175,8 @@ def main() -> int:
     n_atoms = r["n_atoms"]
     value = n_atoms * burst * steps / r["elapsed"]
     lanes = r["info1"]["lanes_per_atom"]
+    # achievable rates of this device (a copy kernel, FMA chains), after the timed region
+    dev = None if args.no_device_probe else P.measure_device(1 << 30, 10)
     flops_launch = FLOPS_FORCE_PER_PAIR * r["pairs"]
     achieved = flops_launch / (r["k_ms"] * 1e-3) / 1e12 if r["k_ms"] > 0 else None
     peak = PEAK_TFLOPS[precision]
@@ -192,6 +196,11 @@ def main() -> int:
         "unique_pairs_in_rc": r["pairs"],
         "list_entries": r["entries"],
     }
+    if dev:
+        # the same kernel against what FMA chains reach here (one FMA per instruction: no packed FP32)
+        reach = dev["fma64_TFLOPs"] if precision == 0 else dev["fma32_TFLOPs"]
+        roofline["achievable_peak"] = reach
+        roofline["frac_of_achievable"] = (achieved / reach) if achieved else None
     out = {
         "metric": "atom-steps/s (EAM force+integrate) and % HBM roofline; FP32-mixed vs FP64",
         "value": value,
@@ -219,6 +228,7 @@ def main() -> int:
         },
         "hbm_frac_algorithmic": BYTES_PER_ATOM_STEP[precision] * value / 1e9 / HBM_PEAK_GBS,
         "roofline": roofline,
+        "device_measured": dev,
         "run_stats": {
             "list_builds": r["info1"]["list_builds"] - r["info0"]["list_builds"],
             "sorts": r["info1"]["sorts"] - r["info0"]["sorts"],

@@ -392,6 +392,17 @@ ptamd_status ptamd_autotune(ptamd_system *sys, int64_t probe_steps, int32_t use_
  * flop count), per replica summed. */
 ptamd_status ptamd_count_pairs(ptamd_system *sys, int64_t *pairs_in_rc, int64_t *list_entries);
 
+/* Achievable rates of the current device, as context for the rooflines
+ * (no part of the MD path): a streaming copy of bytes (a multiple of 16,
+ * at least 1 MiB; float4 loads and stores; read plus write counted) in
+ * GB/s, and independent FMA chains in FP32 (one FMA per instruction: the
+ * library is built without packed FP32) and in FP64 in TFLOP/s, each the
+ * best of reps (>= 1) launches timed with HIP events after one untimed
+ * launch.  Allocates 2 x bytes of device memory for the copy and frees it
+ * before returning.  Outputs may be NULL. */
+ptamd_status ptamd_measure_device(int64_t bytes, int32_t reps, double *copy_gbs, double *fma32_tflops,
+                                  double *fma64_tflops);
+
 const char *ptamd_last_error(void);
 const char *ptamd_version(void);
 

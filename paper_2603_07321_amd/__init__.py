@@ -173,6 +173,7 @@ SIGNATURES = {
     "ptamd_kernel_timing": [_SYS, _D, _D, C.POINTER(C.c_int64), C.c_int32],
     "ptamd_autotune": [_SYS, C.c_int64, C.c_int32, C.POINTER(C.c_int32), _D, _D],
     "ptamd_count_pairs": [_SYS, C.POINTER(C.c_int64), C.POINTER(C.c_int64)],
+    "ptamd_measure_device": [C.c_int64, C.c_int32, _D, _D, _D],
     "ptamd_last_error": [],
     "ptamd_version": [],
 }
@@ -453,6 +454,14 @@ def autotune(sys: int, probe_steps: int = 100, use_cache: bool = True) -> dict:
     l, sk, ms = C.c_int32(), C.c_double(), C.c_double()
     _check(_lib.ptamd_autotune(sys, probe_steps, int(use_cache), C.byref(l), C.byref(sk), C.byref(ms)))
     return {"lanes_per_atom": l.value, "skin": sk.value, "ms_per_step": ms.value}
+
+
+def measure_device(nbytes: int = 1 << 30, reps: int = 10) -> dict:
+    """Achievable copy bandwidth (GB/s) and FP32/FP64 FMA rates (TFLOP/s) of
+    the current device (ptamd_measure_device)."""
+    cp, f32, f64 = C.c_double(), C.c_double(), C.c_double()
+    _check(_lib.ptamd_measure_device(nbytes, reps, C.byref(cp), C.byref(f32), C.byref(f64)))
+    return {"copy_GBs": cp.value, "fma32_TFLOPs": f32.value, "fma64_TFLOPs": f64.value}
 
 
 def count_pairs(sys: int):

@@ -1772,4 +1772,47 @@ void launch_count_pairs(const Params &p, const Buffers &b, int precision, hipStr
   hipLaunchKernelGGL(k_count_pairs<double>, dim3(tiles(p)), dim3(kBlock), 0, s, p, b);
 }
 
+// ---------------------------------------------------------------------------
+// device probes (achievable rates, for context next to the rooflines)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_probe_copy(const float4 *src, float4 *dst, int64_t n) {
+  for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < n; t += (int64_t)gridDim.x * kBlock)
+    dst[t] = src[t];
+}
+
+// kProbeChains independent FMA chains per thread (one FMA per instruction:
+// this code is built without packed FP32), their sum stored so that none
+// is optimised away
+constexpr int kProbeChains = 8;
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_probe_fma(T *out, T mul, T add, int32_t iters) {
+  T a[kProbeChains];
+#pragma unroll
+  for (int c = 0; c < kProbeChains; ++c) a[c] = (T)(threadIdx.x + c);
+  for (int32_t it = 0; it < iters; ++it)
+#pragma unroll
+    for (int c = 0; c < kProbeChains; ++c) a[c] = fma(a[c], mul, add);
+  T sum = (T)0;
+#pragma unroll
+  for (int c = 0; c < kProbeChains; ++c) sum += a[c];
+  out[(size_t)blockIdx.x * kBlock + threadIdx.x] = sum;
+}
+
+void launch_probe_copy(const void *src, void *dst, int64_t bytes, hipStream_t s) {
+  const int64_t n = bytes / (int64_t)sizeof(float4);
+  const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock, 8192));
+  hipLaunchKernelGGL(k_probe_copy, dim3(g), dim3(kBlock), 0, s, static_cast<const float4 *>(src),
+                     static_cast<float4 *>(dst), n);
+}
+
+double launch_probe_fma(void *out, int fp64, int32_t blocks, int32_t iters, hipStream_t s) {
+  if (fp64)
+    hipLaunchKernelGGL(k_probe_fma<double>, dim3(blocks), dim3(kBlock), 0, s, static_cast<double *>(out), 0.999999,
+                       1e-7, iters);
+  else
+    hipLaunchKernelGGL(k_probe_fma<float>, dim3(blocks), dim3(kBlock), 0, s, static_cast<float *>(out), 0.999999f,
+                       1e-7f, iters);
+  return 2.0 * kProbeChains * (double)iters * (double)blocks * kBlock;  // flops
+}
+
 }  // namespace ptamd

@@ -216,5 +216,9 @@ void launch_permute(const Params &p, const Buffers &b, const Buffers &scratch, c
 void launch_strain(const Params &p, const Buffers &b, const double *factor, hipStream_t s);
 void launch_fill_i64(unsigned long long *ptr, int64_t n, unsigned long long v, hipStream_t s);
 void launch_count_pairs(const Params &p, const Buffers &b, int precision, hipStream_t s);
+// device probes: a streaming copy of bytes; FMA chains (returns the flops of one launch; out holds
+// blocks * kBlock elements of the chosen type)
+void launch_probe_copy(const void *src, void *dst, int64_t bytes, hipStream_t s);
+double launch_probe_fma(void *out, int fp64, int32_t blocks, int32_t iters, hipStream_t s);
 
 }  // namespace ptamd

@@ -1698,4 +1698,58 @@ ptamd_status ptamd_count_pairs(ptamd_system *sys, int64_t *pairs_in_rc, int64_t 
   });
 }
 
+ptamd_status ptamd_measure_device(int64_t bytes, int32_t reps, double *copy_gbs, double *fma32_tflops,
+                                  double *fma64_tflops) {
+  void *src = nullptr, *dst = nullptr, *out = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  const ptamd_status st = guard([&] {
+    if (bytes < (1 << 20) || bytes % 16 != 0 || reps < 1) fail(PTAMD_EINVAL, "need bytes >= 1 MiB, a multiple of 16, reps >= 1");
+    int dev = 0;
+    require_device(&dev);
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    // the best of reps timed launches (after one untimed), in ms
+    auto best_ms = [&](auto launch) {
+      launch();
+      float best = 1e30f;
+      for (int32_t k = 0; k < reps; ++k) {
+        HIPCHK(hipEventRecord(e0, nullptr));
+        launch();
+        HIPCHK(hipEventRecord(e1, nullptr));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        best = std::min(best, ms);
+      }
+      check_launch();
+      return (double)best;
+    };
+    if (copy_gbs) {
+      HIPCHK(hipMalloc(&src, (size_t)bytes));
+      HIPCHK(hipMalloc(&dst, (size_t)bytes));
+      HIPCHK(hipMemset(src, 0, (size_t)bytes));
+      const double ms = best_ms([&] { launch_probe_copy(src, dst, bytes, nullptr); });
+      *copy_gbs = 2.0 * (double)bytes / (ms * 1e-3) / 1e9;
+    }
+    // 8 wavefronts per SIMD on every compute unit, each thread 8 chains of 4096 FMAs
+    int cus = 0;
+    HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const int32_t blocks = std::max(1, cus) * 8, iters = 4096;
+    HIPCHK(hipMalloc(&out, (size_t)blocks * kBlock * sizeof(double)));
+    for (int fp64 = 0; fp64 < 2; ++fp64) {
+      double *res = fp64 ? fma64_tflops : fma32_tflops;
+      if (!res) continue;
+      double flops = 0.0;
+      const double ms = best_ms([&] { flops = launch_probe_fma(out, fp64, blocks, iters, nullptr); });
+      *res = flops / (ms * 1e-3) / 1e12;
+    }
+  });
+  if (src) (void)hipFree(src);
+  if (dst) (void)hipFree(dst);
+  if (out) (void)hipFree(out);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  return st;
+}
+
 }  // extern "C"
