@@ -809,6 +809,7 @@ __device__ void build_one(const Params &p, const Buffers &b, int64_t i, int lane
   const size_t slot_base = (size_t)self * (LPA * kGroup);
   const size_t group_stride = (size_t)p.nbr_stride * kGroup;
   int cnt = 0;
+  bool wide = false;  // an offset beyond 16 bits met (reported once per atom below)
   for (int q = 0; q < 25; ++q) {
     const int src = gbase + (q % KB);
     int rq = rs[0], eq = re[0];
@@ -845,7 +846,7 @@ __device__ void build_one(const Params &p, const Buffers &b, int64_t i, int lane
           if (L16) {
             const int d = j - self;
             const bool fits = d >= -32767 && d <= 32767;
-            if (!fits) set_err(b, E_WIDE);
+            wide |= !fits;
             reinterpret_cast<int16_t *>(b.nbr)[(size_t)(sl / kGroup16) * (size_t)p.nbr_stride * kGroup16 +
                                                (size_t)self * (LPA * kGroup16) + l * kGroup16 + sl % kGroup16] =
                 (int16_t)(fits ? d : kOffSentinel);
@@ -857,6 +858,7 @@ __device__ void build_one(const Params &p, const Buffers &b, int64_t i, int lane
       }
     }
   }
+  if (L16 && ((__ballot(wide) >> gbase) & gmask) != 0 && lane == 0) set_err(b, E_WIDE);
   const bool over = cnt > cap;  // cnt is the same in all KB lanes (ballot counts)
   if (over) cnt = cap;
   // pad to whole passes with the sentinel (cap is a multiple of kPass * LPA)
