@@ -1045,21 +1045,27 @@ __global__ __launch_bounds__(kBlock) void k_force(Params p, Buffers b, int32_t k
   if (p.conv && b.acc[r].conv_step != 0) return;  // converged replica: frozen
   const uint8_t g = b.group[i];
   const bool real = g != kPad;
-  // mixed form: the state the epilogue needs for the next position, read
-  // ahead of the pair loop
+  // the state the epilogue needs, read ahead of the pair loop: z for the
+  // virial, and in the mixed form what the next position takes
   double x = 0.0, y = 0.0, z = 0.0, vx = 0.0, vy = 0.0, vz = 0.0;
-  if (p.fold && real && lane == 0) {
-    x = b.x[i]; y = b.y[i]; z = b.z[i];
-    vx = b.vx[i]; vy = b.vy[i]; vz = b.vz[i];
+  if (real && lane == 0) {
+    z = b.z[i];
+    if (p.fold) {
+      x = b.x[i]; y = b.y[i];
+      vx = b.vx[i]; vy = b.vy[i]; vz = b.vz[i];
+    }
   }
   const double eshift = (NM != 2 && real && lane == 0) ? b.eshift[i] : 0.0;  // read ahead too
   const V4 *p4 = reinterpret_cast<const V4 *>(b.pos4);
+  // The virial W_zz = 1/2 sum_ij (z_i - z_j) F_ij,z equals sum_i z_i F_i,z
+  // for these pair-antisymmetric internal forces, so it is formed per atom
+  // after the loop instead of per pair.
   // Sutton-Chen, with w_j = -m B'_j from the density pass:
   //   dU/dr = [-n eps (a/r)^n + (w_i + w_j) (a/r)^m] / r - (dVc - (w_i + w_j) drhoc / m)
   // and the pair energy V - Vc - (r - rc) dVc summed as sum(-n V) here and
   // the shift, which the density pass formed from its sums of r and of the
   // pairs.  Tables: B' as is.
-  R fx = 0, fy = 0, fz = 0, ep = 0, w = 0;
+  R fx = 0, fy = 0, fz = 0, ep = 0;
   if (real) {
     const V4 pi = p4[i];
     const R rc2 = (R)p.rc2, a = (R)p.a;
@@ -1103,7 +1109,6 @@ __global__ __launch_bounds__(kBlock) void k_force(Params p, Buffers b, int32_t k
           fx += f * dx;
           fy += f * dy;
           fz += f * dz;
-          w += f * dz * dz;
         }
       }
     });
@@ -1114,7 +1119,6 @@ __global__ __launch_bounds__(kBlock) void k_force(Params p, Buffers b, int32_t k
     fy += __shfl_xor(fy, o);
     fz += __shfl_xor(fz, o);
     ep += __shfl_xor(ep, o);
-    w += __shfl_xor(w, o);
   }
   long long q[kNQ] = {0, 0, 0, 0, 0, 0, 0, 0};
   if (lane == 0 && real) {
@@ -1158,7 +1162,7 @@ __global__ __launch_bounds__(kBlock) void k_force(Params p, Buffers b, int32_t k
     // pair energy of the atom: tables sum V; Sutton-Chen sums -n V, plus the shift
     const double epair = (NM == 2) ? (double)ep : -(double)ep / p.n + eshift;
     q[Q_EPAIR] = to_fix(0.5 * epair);
-    q[Q_WZZ] = to_fix(-0.5 * (double)w);
+    q[Q_WZZ] = to_fix(z * Fz);
     if (g == 2) q[Q_RZ] = to_fix(-Fz);
   }
   block_atoms_add<kNQ, kBlock / LPA>(q, lane == 0, threadIdx.x / LPA,
