@@ -345,6 +345,13 @@ ptamd_status ptamd_get_strain(const ptamd_system *sys, double *strain /* n_repli
  * pe and wzz have n_replicas entries. */
 ptamd_status ptamd_compute_forces(ptamd_system *sys, double *fx, double *fy, double *fz, double *pe,
                                   double *wzz);
+/* The internal forces F^int of Eq. (f_int) (before any constraint) that the
+ * device holds now: those of the last force pass, i.e. after a burst the
+ * forces at its final positions as the burst's last step computed them
+ * (in the mixed form from the folded step's density pass), without
+ * recomputing anything.  fx, fy, fz: caller-owned, n_atoms each, original
+ * atom order.  PTAMD_EINVAL on a null argument. */
+ptamd_status ptamd_get_forces(ptamd_system *sys, double *fx, double *fy, double *fz);
 /* Spatially sorts and rebuilds the Verlet list at the current positions and
  * returns it as CSR in original indices, each row ascending: offsets has
  * n+1 entries, idx has cap entries.  Returns PTAMD_EOVERFLOW (with

@@ -108,6 +108,7 @@ def lib():
     L.orc_run_burst.restype = C.c_int32
     L.orc_run_burst.argtypes = [C.POINTER(_State), C.POINTER(SC), C.POINTER(MD), C.c_int64,
                                 C.POINTER(Averages), C.c_void_p, C.c_void_p]
+    L.orc_block_se.argtypes = [_dp, C.c_int64, C.c_int64, C.POINTER(C.c_double)]
     L.orc_apply_strain.argtypes = [C.POINTER(_State), C.c_double]
     L.orc_observables.argtypes = [C.POINTER(_State), C.POINTER(SC)] + [C.POINTER(C.c_double)] * 4
     _lib = L
@@ -335,3 +336,12 @@ def observables(st: State, p: SC):
     out = [C.c_double() for _ in range(4)]
     lib().orc_observables(C.byref(cs), C.byref(p), *[C.byref(o) for o in out])
     return dict(zip(("K", "U", "szz", "tz"), (o.value for o in out)))
+
+
+def block_se(series) -> float:
+    """Standard error of the mean of a 1-D series from 20 batch means
+    (the oracle's burst standard error, NaN below 20 samples)."""
+    a = np.ascontiguousarray(series, dtype=np.float64)
+    out = C.c_double()
+    lib().orc_block_se(a, 1, len(a), C.byref(out))
+    return out.value

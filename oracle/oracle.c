@@ -460,7 +460,10 @@ void orc_observables(const orc_state *s, const orc_sc *p, double *K, double *U, 
     free(f);
 }
 
-static void block_se(const double *col, int64_t stride, int64_t n, double *se) {
+/* Standard error of the mean of a series (column col, every stride-th
+ * value, n values) from 20 batch means of n / 20 samples each (the samples
+ * beyond 20 (n / 20) are not used): sqrt(sum_b (m_b - mbar)^2 / (20 * 19)). */
+void orc_block_se(const double *col, int64_t stride, int64_t n, double *se) {
     const int64_t nb = 20;
     if (n < nb) { *se = NAN; return; }
     const int64_t bs = n / nb;
@@ -572,9 +575,9 @@ int32_t orc_run_burst(orc_state *s, const orc_sc *p, const orc_md *md, int64_t n
         avg->ke = sk * inv; avg->pe = su * inv; avg->szz = ss * inv;
         avg->tz = stz * inv; avg->temp = st * inv;
         avg->n_samples = n_steps;
-        block_se(ser + ORC_SER_K, ORC_SER_NCOL, n_steps, &avg->ke_se);
-        block_se(ser + ORC_SER_U, ORC_SER_NCOL, n_steps, &avg->pe_se);
-        block_se(ser + ORC_SER_SZZ, ORC_SER_NCOL, n_steps, &avg->szz_se);
+        orc_block_se(ser + ORC_SER_K, ORC_SER_NCOL, n_steps, &avg->ke_se);
+        orc_block_se(ser + ORC_SER_U, ORC_SER_NCOL, n_steps, &avg->pe_se);
+        orc_block_se(ser + ORC_SER_SZZ, ORC_SER_NCOL, n_steps, &avg->szz_se);
     }
     free(fx); free(fy); free(fz); free(own);
     return status;

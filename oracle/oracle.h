@@ -136,6 +136,9 @@ enum { ORC_SER_K = 0, ORC_SER_U, ORC_SER_SZZ, ORC_SER_T, ORC_SER_LAMBDA, ORC_SER
  * pos_sum (3n: x sums, then y, then z; may be NULL) receives the sum over the
  * samples r = 1..n_steps of every atom's position, the numerator of
  * Eq. (mean_pos).  Returns 0, or -7 if the thermostat meets T <= 0. */
+/* Standard error of the mean from 20 batch means (NaN when n < 20). */
+void orc_block_se(const double *col, int64_t stride, int64_t n, double *se);
+
 int32_t orc_run_burst(orc_state *s, const orc_sc *p, const orc_md *md, int64_t n_steps,
                       orc_averages *avg, double *series, double *pos_sum);
 /* eps_k = eps_{k-1} + d_eps; z <- z (1+eps_k)/(1+eps_{k-1}) for every atom. */

@@ -165,6 +165,7 @@ SIGNATURES = {
     "ptamd_set_state": [_SYS, _P, _P, _P, _P, _P, _P],
     "ptamd_get_strain": [_SYS, _P],
     "ptamd_compute_forces": [_SYS, _P, _P, _P, _P, _P],
+    "ptamd_get_forces": [_SYS, _P, _P, _P],
     "ptamd_get_neighbors": [_SYS, _P, _P, C.c_int64],
     "ptamd_get_cells": [_SYS, _P, _P, _P, _P],
     "ptamd_get_series": [_SYS, C.c_int32, _P, C.c_int64],
@@ -403,6 +404,13 @@ def compute_forces(sys: int) -> dict:
     return {"fx": f[0], "fy": f[1], "fz": f[2], "U": pe, "Wzz": w}
 
 
+def get_forces(sys: int) -> dict:
+    n = get_num_atoms(sys)
+    f = [np.zeros(n, np.float64) for _ in range(3)]
+    _check(_lib.ptamd_get_forces(sys, *[_ptr(a) for a in f]))
+    return {"fx": f[0], "fy": f[1], "fz": f[2]}
+
+
 def get_neighbors(sys: int):
     n = get_num_atoms(sys)
     off = np.zeros(n + 1, np.int64)
@@ -559,6 +567,9 @@ class System:
 
     def compute_forces(self):
         return compute_forces(self.h)
+
+    def get_forces(self):
+        return get_forces(self.h)
 
     def get_neighbors(self):
         return get_neighbors(self.h)

@@ -1117,8 +1117,8 @@ static void set_state(ptamd_system *s, const double *x, const double *y, const d
   s->stats_valid = false;
 }
 
-static void compute_forces(ptamd_system *s, double *fx, double *fy, double *fz, double *pe, double *wzz) {
-  initial_forces(s);
+// forces held on the device (original order): those of the last force pass
+static void read_forces(ptamd_system *s, double *fx, double *fy, double *fz) {
   const int64_t N = s->ntot;
   std::vector<int32_t> o(N);
   std::vector<double> t(N);
@@ -1131,6 +1131,13 @@ static void compute_forces(ptamd_system *s, double *fx, double *fy, double *fz, 
     for (int64_t i = 0; i < N; ++i)
       if (o[i] >= 0) dst[k][o[i]] = t[i];
   }
+}
+
+static void compute_forces(ptamd_system *s, double *fx, double *fy, double *fz, double *pe, double *wzz) {
+  initial_forces(s);
+  read_forces(s, fx, fy, fz);
+  const int64_t N = s->ntot;
+  (void)N;
   const size_t nsl = (size_t)s->n_rep * kSlots * kNQ;
   std::vector<unsigned long long> sl(nsl);
   d2h(s, sl.data(), s->B.slots, nsl * 8);  // parity 0
@@ -1595,6 +1602,14 @@ ptamd_status ptamd_compute_forces(ptamd_system *sys, double *fx, double *fy, dou
   return guard([&] {
     use_device(sys);
     compute_forces(sys, fx, fy, fz, pe, wzz);
+  });
+}
+
+ptamd_status ptamd_get_forces(ptamd_system *sys, double *fx, double *fy, double *fz) {
+  return guard([&] {
+    if (!sys || !fx || !fy || !fz) fail(PTAMD_EINVAL, "null argument");
+    use_device(sys);
+    read_forces(sys, fx, fy, fz);
   });
 }
 

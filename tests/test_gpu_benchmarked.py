@@ -1,0 +1,224 @@
+"""Parity at the configurations the benchmark runs, element by element.
+
+  - the 4,000-atom FP64 cube (10^3 cells, 300 K, seed 1) at 16 lanes per
+    atom: forces, energy and virial at steps 0, 1, 10 and 100 and the
+    trajectory in between, then a whole 200-step burst's averages, against
+    the oracle from the same initial state (Sec. 2.3 Eqs. (pe), (f_int);
+    Eqs. (vv_algo_*); Sec. 2.2 Eq. (R_m_t));
+  - the same cube over a 4,000-step burst: averages of the FP64 and the
+    mixed form against the oracle's within their sampling error,
+    |delta| <= 3 sqrt(SE_gpu^2 + SE_oracle^2) (20-batch standard errors);
+  - the 62,500-atom cube (25^3 cells) after a +1e-4 strain increment and a
+    burst: every atom's force, and U and W_zz, against the oracle on the
+    GPU's state, in the benchmark's launch shape (mixed, folded step, 16-bit
+    lists) and in FP64; the forces checked are both those the burst's last
+    step computed and a fresh evaluation; and a 100-step FP64 trajectory;
+  - the 500,000-atom cube (50^3 cells) after a -1e-4 increment and a burst,
+    mixed: every atom's force against the oracle.
+
+Bars: FP64 per-atom force |dF| <= 1e-5 max(|F_ref|, F_rms), energy
+1e-6 eV/atom, W_zz 1e-8 relative, trajectories |dr| <= 1e-8 A and
+|dv| <= 1e-10 A/fs; mixed per-atom force 2e-4, energy 1e-5 eV/atom, W_zz
+1e-4 relative.  The measured errors are printed.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_2603_07321_amd")
+
+A = 4.05
+
+
+def _orc():
+    import oracle
+    return oracle
+
+
+def _ostate(st, nc, strain=0.0):
+    O = _orc()
+    _, _, _, g, _ = O.fcc_cube(nc, A, True)
+    return O.State(st["x"].copy(), st["y"].copy(), st["z"].copy(), st["vx"].copy(), st["vy"].copy(),
+                   st["vz"].copy(), g, float(nc) ** 3 * A ** 3, (nc * A) ** 2, strain)
+
+
+def _force_err(g, ref):
+    """Largest and rms per-atom error relative to max(|F_ref|, F_rms)."""
+    F = np.stack([ref["fx"], ref["fy"], ref["fz"]], 1)
+    G = np.stack([g["fx"], g["fy"], g["fz"]], 1)
+    frms = np.sqrt((F ** 2).sum(1).mean())
+    e = np.linalg.norm(G - F, axis=1) / np.maximum(np.linalg.norm(F, axis=1), frms)
+    return float(e.max()), float(np.sqrt((e ** 2).mean()))
+
+
+def _w_err(w, ref_w):
+    return abs(w - ref_w) / max(abs(ref_w), 1.0)
+
+
+# --------------------------------------------------------------------------
+# the 4,000-atom FP64 cube at 16 lanes per atom
+# --------------------------------------------------------------------------
+def test_cfg1_cube10_fp64_16_lanes_end_to_end():
+    O = _orc()
+    p = O.sc_params()
+    md = P.md_params(precision=0, lanes_per_atom=16)
+    with P.System.cube(10, T0=300.0, seed=1, md=md) as g:
+        assert g.info()["lanes_per_atom"] == 16
+        st0 = g.get_state()
+        ost = _ostate(st0, 10)
+        n = len(st0["x"])
+        f = g.compute_forces()
+        ref = O.forces(ost.x, ost.y, ost.z, p, ost.group)
+        fe, _ = _force_err(f, ref)
+        ue = abs(f["U"][0] - ref["U"]) / n
+        we = _w_err(f["Wzz"][0], ref["Wzz"])
+        print(f"\nstep 0: force {fe:.2e} U/atom {ue:.2e} W {we:.2e}")
+        assert fe <= 1e-5 and ue <= 1e-6 and we <= 1e-8
+        done = 0
+        for k in (1, 9, 90):
+            avg = g.run_fast_md(k)[0]
+            ser = g.get_series(0, k)
+            st = g.get_state()
+            fb = g.get_forces()
+            ravg, rser = O.run_burst(ost, p, O.md_params(), k, series=True)
+            done += k
+            dr = max(np.abs(st[c] - getattr(ost, c)).max() for c in ("x", "y", "z"))
+            dv = max(np.abs(st[c] - getattr(ost, c)).max() for c in ("vx", "vy", "vz"))
+            # forces the burst's last step computed, against the oracle's at the same positions
+            ref = O.forces(st["x"], st["y"], st["z"], p, ost.group)
+            fe, _ = _force_err(fb, ref)
+            ue = abs(ser[-1, 1] - ref["U"]) / n
+            print(f"step {done}: |dr| {dr:.2e} |dv| {dv:.2e} force {fe:.2e} U/atom {ue:.2e}")
+            assert dr <= 1e-8 and dv <= 1e-10
+            assert fe <= 1e-5 and ue <= 1e-6
+            for c in ("ke", "pe", "szz", "tz"):
+                assert avg[c] == pytest.approx(ravg[c], rel=1e-9, abs=1e-9), (done, c)
+            assert np.allclose(ser[:, :3], rser[:, :3], rtol=1e-9, atol=1e-9)
+    # a whole 200-step burst of the workload from the initial state
+    with P.System.cube(10, T0=300.0, seed=1, md=md) as g:
+        avg = g.run_fast_md(200)[0]
+        st = g.get_state()
+    ost = _ostate(st0, 10)
+    ravg, _ = O.run_burst(ost, p, O.md_params(), 200)
+    dr = max(np.abs(st[c] - getattr(ost, c)).max() for c in ("x", "y", "z"))
+    print(f"200 steps: |dr| {dr:.2e}; KE {avg['ke']:.9f} / {ravg['ke']:.9f}, PE {avg['pe']:.9f} / "
+          f"{ravg['pe']:.9f}, szz {avg['szz']:.9f} / {ravg['szz']:.9f}")
+    assert dr <= 1e-8
+    for c in ("ke", "pe", "szz", "tz", "temp"):
+        assert avg[c] == pytest.approx(ravg[c], rel=1e-9, abs=1e-9), c
+    for c in ("ke_se", "pe_se", "szz_se"):
+        assert avg[c] == pytest.approx(ravg[c], rel=1e-6, abs=1e-9), c
+    assert avg["n_samples"] == 200
+
+
+@pytest.fixture(scope="module")
+def cfg1_long_oracle():
+    """The oracle's 4,000-step burst of the 4,000-atom cube (state from the
+    GPU's create_system, seed 1)."""
+    O = _orc()
+    with P.System.cube(10, T0=300.0, seed=1, md=P.md_params(precision=0)) as g:
+        st0 = g.get_state()
+    ost = _ostate(st0, 10)
+    ravg, _ = O.run_burst(ost, O.sc_params(), O.md_params(), 4000)
+    return st0, ravg, ost
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("precision,lanes", [(0, 16), (1, 4)])
+def test_cfg1_long_burst_within_sampling_error(cfg1_long_oracle, precision, lanes):
+    st0, ravg, ost = cfg1_long_oracle
+    with P.System.cube(10, T0=300.0, seed=1, md=P.md_params(precision=precision, lanes_per_atom=lanes)) as g:
+        assert np.array_equal(g.get_state()["x"], st0["x"])
+        avg = g.run_fast_md(4000)[0]
+        st = g.get_state()
+    dr = max(np.abs(st[c] - getattr(ost, c)).max() for c in ("x", "y", "z"))
+    print(f"\nprecision {precision}: final |dr| vs oracle {dr:.2e} A")
+    for c, se in (("ke", "ke_se"), ("pe", "pe_se"), ("szz", "szz_se")):
+        tol = 3.0 * np.hypot(avg[se], ravg[se])
+        d = avg[c] - ravg[c]
+        print(f"  {c}: gpu {avg[c]:.8g} +- {avg[se]:.2e}, oracle {ravg[c]:.8g} +- {ravg[se]:.2e}, "
+              f"delta {d:.2e} (bar {tol:.2e})")
+        assert np.isfinite(tol) and abs(d) <= tol
+
+
+# --------------------------------------------------------------------------
+# the 62,500-atom cube, all atoms
+# --------------------------------------------------------------------------
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("precision,lanes,skin", [(1, 4, 1.5), (1, 2, 1.0), (0, 4, 1.0)])
+def test_cube25_every_atom(precision, lanes, skin):
+    O = _orc()
+    p = O.sc_params()
+    md = P.md_params(precision=precision, lanes_per_atom=lanes, skin=skin)
+    with P.System.cube(25, T0=300.0, seed=1, md=md) as g:
+        g.apply_strain_increment(1e-4)
+        g.run_fast_md(60)
+        info = g.info()
+        st = g.get_state()
+        ser = g.get_series(0, 60)
+        fb = g.get_forces()
+        f = g.compute_forces()
+    if precision == 1:
+        assert info["folded"] == 1 and info["list_index_bits"] == 16
+    _, _, _, group, _ = O.fcc_cube(25, A, True)
+    ref = O.forces(st["x"], st["y"], st["z"], p, group)
+    n = len(st["x"])
+    fe_b, fr_b = _force_err(fb, ref)
+    fe, fr = _force_err(f, ref)
+    ue_b = abs(ser[-1, 1] - ref["U"]) / n
+    ue = abs(f["U"][0] - ref["U"]) / n
+    we = _w_err(f["Wzz"][0], ref["Wzz"])
+    G = np.stack([f["fx"], f["fy"], f["fz"]], 1)
+    print(f"\nN={n} precision={precision} lanes={lanes} skin={skin}: burst's last forces max {fe_b:.2e} rms {fr_b:.2e}; "
+          f"fresh forces max {fe:.2e} rms {fr:.2e}; U/atom {ue_b:.2e} (burst) {ue:.2e} (fresh); W_zz {we:.2e} "
+          f"({f['Wzz'][0]:.6f} / {ref['Wzz']:.6f}); |sum F| {np.abs(G.sum(0)).max():.2e}")
+    bar_f, bar_u, bar_w = (2e-4, 1e-5, 1e-4) if precision else (1e-5, 1e-6, 1e-8)
+    assert fe_b <= bar_f and fe <= bar_f
+    assert ue_b <= bar_u and ue <= bar_u
+    assert we <= bar_w
+
+
+@pytest.mark.timeout(900)
+def test_cube25_fp64_100_step_trajectory():
+    O = _orc()
+    md = P.md_params(precision=0, lanes_per_atom=4)
+    with P.System.cube(25, T0=300.0, seed=1, md=md) as g:
+        st0 = g.get_state()
+        g.apply_strain_increment(1e-4)
+        avg = g.run_fast_md(100)[0]
+        st = g.get_state()
+    ost = _ostate(st0, 25)
+    O.apply_strain(ost, 1e-4)
+    ravg, _ = O.run_burst(ost, O.sc_params(), O.md_params(), 100)
+    dr = max(np.abs(st[c] - getattr(ost, c)).max() for c in ("x", "y", "z"))
+    dv = max(np.abs(st[c] - getattr(ost, c)).max() for c in ("vx", "vy", "vz"))
+    print(f"\n62,500 atoms, 100 FP64 steps: |dr| {dr:.2e} |dv| {dv:.2e}")
+    assert dr <= 1e-8 and dv <= 1e-10
+    for c in ("ke", "pe", "szz", "tz"):
+        assert avg[c] == pytest.approx(ravg[c], rel=1e-9, abs=1e-9), c
+
+
+# --------------------------------------------------------------------------
+# the 500,000-atom cube, all atoms
+# --------------------------------------------------------------------------
+@pytest.mark.timeout(1200)
+def test_cube50_every_atom_mixed():
+    O = _orc()
+    p = O.sc_params()
+    md = P.md_params(precision=1, lanes_per_atom=4)
+    with P.System.cube(50, T0=300.0, seed=1, md=md) as g:
+        g.apply_strain_increment(-1e-4)
+        g.run_fast_md(20)
+        info = g.info()
+        st = g.get_state()
+        ser = g.get_series(0, 20)
+        fb = g.get_forces()
+    _, _, _, group, _ = O.fcc_cube(50, A, True)
+    ref = O.forces(st["x"], st["y"], st["z"], p, group)
+    n = len(st["x"])
+    fe, fr = _force_err(fb, ref)
+    ue = abs(ser[-1, 1] - ref["U"]) / n
+    print(f"\nN={n} mixed, lists of {info['list_index_bits']}-bit entries: forces max {fe:.2e} rms {fr:.2e}, "
+          f"U/atom {ue:.2e}")
+    assert fe <= 2e-4 and ue <= 1e-5

@@ -1,11 +1,5 @@
-"""Full-size checks in the launch configuration the benchmark times.
-
-At the workloads' real sizes the oracle cannot run whole bursts, so:
-  - forces of sampled atoms are recomputed one by one by the oracle
-    (O(N * nbar) each) from the GPU's state, and compared to the mixed-form
-    bar: |dF| <= 2e-4 max(|F|, F_rms), F_rms from the GPU forces;
-  - properties that hold at any size: internal forces sum to zero (Newton's
-    third law over the whole system);
+"""Full-size checks of the batched workloads and the autotuner (every-atom
+force checks at the benchmark's sizes are in test_gpu_benchmarked.py):
   - batched replicas against individual runs: mixed batch vs FP64 runs of the
     same replicas, burst averages within three combined block standard errors
     (plus a small absolute floor);
@@ -22,61 +16,6 @@ P = pytest.importorskip("paper_2603_07321_amd")
 def _orc():
     import oracle
     return oracle
-
-
-def _sample_atoms(st, group, k, seed):
-    """Atoms spread over the cube: interior, surface, both fixed regions."""
-    rng = np.random.default_rng(seed)
-    n = len(st["x"])
-    idx = set(rng.choice(n, k, replace=False).tolist())
-    idx.add(int(np.argmin(st["x"])))            # a surface atom
-    idx.update(np.where(group == 1)[0][:1].tolist())
-    idx.update(np.where(group == 2)[0][-1:].tolist())
-    return sorted(idx)
-
-
-@pytest.mark.parametrize("nc,precision,lanes,steps", [(25, 1, 4, 60), (25, 1, 8, 60), (25, 0, 4, 30)])
-def test_cube25_sampled_forces(nc, precision, lanes, steps):
-    O = _orc()
-    md = P.md_params(precision=precision, lanes_per_atom=lanes)
-    with P.System.cube(nc, T0=300.0, seed=1, md=md) as g:
-        g.apply_strain_increment(1e-4)
-        g.run_fast_md(steps)
-        st = g.get_state()
-        f = g.compute_forces()
-    _, _, _, group, _ = O.fcc_cube(nc, 4.05, True)
-    G = np.stack([f["fx"], f["fy"], f["fz"]], 1)
-    frms = np.sqrt((G ** 2).sum(1).mean())
-    # Newton's third law over the whole (unconstrained) internal force field
-    assert np.abs(G.sum(0)).max() < (1e-3 if precision else 1e-9) * frms * np.sqrt(len(G))
-    bar = 2e-4 if precision else 1e-5
-    worst = 0.0
-    for i in _sample_atoms(st, group, 10, 7):
-        ref = O.atom_force(st["x"], st["y"], st["z"], O.sc_params(), i)
-        err = np.linalg.norm(G[i] - ref) / max(np.linalg.norm(ref), frms)
-        worst = max(worst, err)
-    print(f"\nN={len(G)} precision={precision} lanes={lanes}: worst sampled force error {worst:.2e}")
-    assert worst <= bar
-
-
-def test_cube50_sampled_forces():
-    """500,000-atom cube (the compression workload's size), mixed form."""
-    O = _orc()
-    md = P.md_params(precision=1, lanes_per_atom=2)
-    with P.System.cube(50, T0=300.0, seed=1, md=md) as g:
-        g.apply_strain_increment(-1e-4)
-        g.run_fast_md(20)
-        st = g.get_state()
-        f = g.compute_forces()
-    _, _, _, group, _ = O.fcc_cube(50, 4.05, True)
-    G = np.stack([f["fx"], f["fy"], f["fz"]], 1)
-    frms = np.sqrt((G ** 2).sum(1).mean())
-    worst = 0.0
-    for i in _sample_atoms(st, group, 3, 11):
-        ref = O.atom_force(st["x"], st["y"], st["z"], O.sc_params(), i)
-        worst = max(worst, np.linalg.norm(G[i] - ref) / max(np.linalg.norm(ref), frms))
-    print(f"\nN=500000 mixed: worst sampled force error {worst:.2e}")
-    assert worst <= 2e-4
 
 
 def test_uneven_mixed_batch_against_individual_fp64():
