@@ -89,7 +89,12 @@ typedef struct {
  * lanes of a wavefront that share one atom's pair sums; 0 = chosen from the
  * atom count (ptamd_autotune() measures instead), else 1, 2, 4, 8 or 16.  thermostat: 0 = NVE,
  * 1 = Berendsen with coupling time tau_fs (> 0), applied to the mobile atoms
- * at the end of each step. */
+ * at the end of each step.  full_lists: 0 (default) = every fourth step the
+ * density pass prunes the Verlet lists to the pairs within rc plus what the
+ * fastest atoms can close in the steps until the next pruning, and the pair
+ * passes in between read those; 1 = the pair passes read the full Verlet
+ * lists every step.  Results do not depend on it beyond rounding (every pair
+ * term still tests r < rc). */
 typedef struct {
     double dt_fs;
     double tau_fs;
@@ -97,6 +102,7 @@ typedef struct {
     int32_t precision;
     double skin;
     int32_t lanes_per_atom;
+    int32_t full_lists;
 } ptamd_md_params;
 
 /* Burst averages over the samples r = 1..n (Eq. (R_m_t)); *_se are
@@ -369,16 +375,19 @@ ptamd_status ptamd_get_info(const ptamd_system *sys, ptamd_info *info);
 /* Orders all later device work on stream (a hipStream_t, e.g. torch's
  * current stream on ROCm).  NULL selects the null stream. */
 ptamd_status ptamd_set_stream(ptamd_system *sys, void *hip_stream);
-/* Timing of the force kernel.  The first call switches timing on; from then
- * on the first step of every burst chunk launches the force kernel directly
- * (the rest of the chunk stays a graph): each block stamps the device wall
- * clock at its start and end, and the launch's span (earliest start to latest
- * end) is averaged into avg_ms; the same launches are also bracketed by HIP
- * events on the system's stream (avg_event_ms, which also holds the dispatch
- * latency of a direct launch).  count = launches timed since the last reset.
+/* Timing of the pair kernels (measurement hook).  The first call switches
+ * timing on; from then on the first two steps of every burst chunk of at
+ * least two steps are launched directly (the rest of the chunk stays a
+ * graph; the first of them prunes the lists, the second is an ordinary
+ * step).  The second step's density and force kernels are bracketed by HIP
+ * events on the system's stream: their averages are density_event_ms and
+ * avg_event_ms (each holds the dispatch latency of a direct launch, about a
+ * microsecond).  The force kernel's blocks also stamp the device wall clock
+ * at their start and end, and the launch's span (earliest start to latest
+ * end) is averaged into avg_ms.  count = steps timed since the last reset.
  * Outputs may be NULL. */
-ptamd_status ptamd_kernel_timing(ptamd_system *sys, double *avg_ms, double *avg_event_ms, int64_t *count,
-                                 int32_t reset);
+ptamd_status ptamd_kernel_timing(ptamd_system *sys, double *avg_ms, double *avg_event_ms, double *density_event_ms,
+                                 int64_t *count, int32_t reset);
 /* Autotuner: times probe bursts of probe_steps (>= 10) steps from the
  * current state for lanes per atom in {2, 4, 8, 16} and Verlet skin in
  * {0.6, 0.8, 1.0, 1.5} A, twice each (a candidate counts with its faster
@@ -396,8 +405,13 @@ ptamd_status ptamd_kernel_timing(ptamd_system *sys, double *avg_ms, double *avg_
 ptamd_status ptamd_autotune(ptamd_system *sys, int64_t probe_steps, int32_t use_cache, int32_t *lanes_per_atom,
                             double *skin, double *ms_per_step);
 /* Unique pairs within rc at the current positions (for the algorithmic
- * flop count), per replica summed. */
-ptamd_status ptamd_count_pairs(ptamd_system *sys, int64_t *pairs_in_rc, int64_t *list_entries);
+ * flop count), summed over the replicas; list_entries: entries of the full
+ * Verlet lists; pruned_entries (may be NULL): entries of the pruned lists
+ * as the last pruning pass left them, 0 when the last chunk ran on full
+ * lists; prune_radius (may be NULL): their radius in A (0 then).  Sorts and
+ * rebuilds the lists first if the state changed since the last burst. */
+ptamd_status ptamd_count_pairs(ptamd_system *sys, int64_t *pairs_in_rc, int64_t *list_entries,
+                               int64_t *pruned_entries, double *prune_radius);
 
 /* Achievable rates of the current device, as context for the rooflines
  * (no part of the MD path): a streaming copy of bytes (a multiple of 16,

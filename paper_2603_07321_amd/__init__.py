@@ -57,7 +57,8 @@ class SCParams(C.Structure):
 
 class MDParams(C.Structure):
     _fields_ = [("dt_fs", C.c_double), ("tau_fs", C.c_double), ("thermostat", C.c_int32),
-                ("precision", C.c_int32), ("skin", C.c_double), ("lanes_per_atom", C.c_int32)]
+                ("precision", C.c_int32), ("skin", C.c_double), ("lanes_per_atom", C.c_int32),
+                ("full_lists", C.c_int32)]
 
 
 class Averages(C.Structure):
@@ -171,9 +172,9 @@ SIGNATURES = {
     "ptamd_get_series": [_SYS, C.c_int32, _P, C.c_int64],
     "ptamd_get_info": [_SYS, C.POINTER(Info)],
     "ptamd_set_stream": [_SYS, C.c_void_p],
-    "ptamd_kernel_timing": [_SYS, _D, _D, C.POINTER(C.c_int64), C.c_int32],
+    "ptamd_kernel_timing": [_SYS, _D, _D, _D, C.POINTER(C.c_int64), C.c_int32],
     "ptamd_autotune": [_SYS, C.c_int64, C.c_int32, C.POINTER(C.c_int32), _D, _D],
-    "ptamd_count_pairs": [_SYS, C.POINTER(C.c_int64), C.POINTER(C.c_int64)],
+    "ptamd_count_pairs": [_SYS, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64), _D],
     "ptamd_measure_device": [C.c_int64, C.c_int32, _D, _D, _D],
     "ptamd_last_error": [],
     "ptamd_version": [],
@@ -206,8 +207,9 @@ def sc_params(eps=0.0033147, a=4.05, n=7.0, m=6.0, c=16.399, rc=8.1, shift=2) ->
     return SCParams(eps, a, n, m, c, rc, shift)
 
 
-def md_params(dt_fs=1.0, tau_fs=100.0, thermostat=1, precision=0, skin=1.0, lanes_per_atom=0) -> MDParams:
-    return MDParams(dt_fs, tau_fs, thermostat, precision, skin, lanes_per_atom)
+def md_params(dt_fs=1.0, tau_fs=100.0, thermostat=1, precision=0, skin=1.0, lanes_per_atom=0,
+              full_lists=0) -> MDParams:
+    return MDParams(dt_fs, tau_fs, thermostat, precision, skin, lanes_per_atom, full_lists)
 
 
 def conv_params(lag=1000, n_max=50000, tol=(0.05, 0.05, 0.0, 0.05), floor=(0.0, 0.0, 0.0, 0.0)) -> ConvParams:
@@ -450,12 +452,13 @@ def set_stream(sys: int, stream) -> None:
     _check(_lib.ptamd_set_stream(sys, ptr))
 
 
-def kernel_timing(sys: int, reset: bool = False):
-    """(average force-kernel span in ms from in-kernel device clock stamps,
-    average of the same launches bracketed by HIP events in ms, count)."""
-    ms, ev, cnt = C.c_double(), C.c_double(), C.c_int64()
-    _check(_lib.ptamd_kernel_timing(sys, C.byref(ms), C.byref(ev), C.byref(cnt), int(reset)))
-    return ms.value, ev.value, cnt.value
+def kernel_timing(sys: int, reset: bool = False) -> dict:
+    """Averages over the timed steps, in ms: the force kernel's span from
+    in-kernel device clock stamps, the same launches bracketed by HIP events,
+    the density kernel bracketed by HIP events; and the count of timed steps."""
+    ms, ev, dev, cnt = C.c_double(), C.c_double(), C.c_double(), C.c_int64()
+    _check(_lib.ptamd_kernel_timing(sys, C.byref(ms), C.byref(ev), C.byref(dev), C.byref(cnt), int(reset)))
+    return {"force_ms": ms.value, "force_event_ms": ev.value, "density_event_ms": dev.value, "count": cnt.value}
 
 
 def autotune(sys: int, probe_steps: int = 100, use_cache: bool = True) -> dict:
@@ -472,10 +475,12 @@ def measure_device(nbytes: int = 1 << 30, reps: int = 10) -> dict:
     return {"copy_GBs": cp.value, "fma32_TFLOPs": f32.value, "fma64_TFLOPs": f64.value}
 
 
-def count_pairs(sys: int):
-    p, e = C.c_int64(), C.c_int64()
-    _check(_lib.ptamd_count_pairs(sys, C.byref(p), C.byref(e)))
-    return p.value, e.value
+def count_pairs(sys: int) -> dict:
+    """Unique pairs within rc, full-list entries, pruned-list entries and the
+    pruned lists' radius (A; 0 when the last chunk ran on full lists)."""
+    p, e, q, r = C.c_int64(), C.c_int64(), C.c_int64(), C.c_double()
+    _check(_lib.ptamd_count_pairs(sys, C.byref(p), C.byref(e), C.byref(q), C.byref(r)))
+    return {"pairs_in_rc": p.value, "list_entries": e.value, "pruned_entries": q.value, "prune_radius": r.value}
 
 
 # ---------------------------------------------------------------------------

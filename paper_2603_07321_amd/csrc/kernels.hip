@@ -103,6 +103,15 @@ template <class V4> __device__ __forceinline__ V4 gather(const V4 *base, int j) 
   return *reinterpret_cast<const V4 *>(reinterpret_cast<const char *>(base) + off);
 }
 
+// Origin of the pair kernels' gather copies (pos4, pnext) of a replica's
+// positions: the FP32 copies of the mixed form hold coordinates relative to
+// the cube's centre, so that their rounding (half an ulp of the coordinate)
+// is set by the cube's half-size, not by where the cube sits; the FP64
+// copies are absolute.  Only differences of these coordinates are used.
+template <class R> __device__ __forceinline__ double gorigin(const RepInfo &rp, int d) {
+  return sizeof(R) == sizeof(float) ? rp.center[d] : 0.0;
+}
+
 template <class V4>
 __device__ __forceinline__ void gather8(const V4 *p4, int4 la, int4 lb, V4 (&pj)[8]) {
   const int jv[8] = {la.x, la.y, la.z, la.w, lb.x, lb.y, lb.z, lb.w};
@@ -117,36 +126,43 @@ __device__ __forceinline__ void gather8(const V4 *p4, int4 la, int4 lb, V4 (&pj)
 // them, and their latency (the list streams from HBM or the Infinity Cache)
 // hides behind this pass's arithmetic.  The scheduling barriers keep that
 // issue order.  (Gathering the next pass's positions ahead as well, into a
-// second buffer, measured slower on the 62,500-atom cube.)  body(pj)
-// evaluates eight gathered entries.
-// Index of a 16-bit list entry w of atom self (sent: the sentinel's).
-__device__ __forceinline__ int off_index(int w, int self, int sent) {
-  return w == kOffSentinel ? sent : self + w;
+// second buffer, measured slower on the 62,500-atom cube.)  body(pj, raw)
+// evaluates eight gathered entries; raw holds the entries as stored (the
+// pruning density pass copies them into the pruned list).
+// Index of a 16-bit list entry w of an atom whose offsets count from base
+// (sent: the sentinel's index).
+__device__ __forceinline__ int off_index(unsigned w, int base, int sent) {
+  return w == (unsigned)kOffSentinel ? sent : base + (int)w;
 }
 
 // L16: the 16-bit form, one 16-byte group (eight offsets) per pass.
 template <bool L16, class V4, class Body>
-__device__ __forceinline__ void pair_passes(const V4 *p4, const int4 *nb4, int64_t stride, int npl, int self,
+__device__ __forceinline__ void pair_passes(const V4 *p4, const int4 *nb4, int64_t stride, int npl, int base,
                                             int sent, Body &&body) {
   V4 pj[8];
+  int raw[8];
   if (L16) {
     int4 la = nb4[0];
     for (int s = 0; s < npl; s += kPass) {
-      const int w[4] = {la.x, la.y, la.z, la.w};
+      const unsigned w[4] = {(unsigned)la.x, (unsigned)la.y, (unsigned)la.z, (unsigned)la.w};
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        pj[2 * u] = gather<V4>(p4, off_index((int)(short)(w[u] & 0xffff), self, sent));
-        pj[2 * u + 1] = gather<V4>(p4, off_index(w[u] >> 16, self, sent));
+        raw[2 * u] = (int)(w[u] & 0xffffu);
+        raw[2 * u + 1] = (int)(w[u] >> 16);
+        pj[2 * u] = gather<V4>(p4, off_index(w[u] & 0xffffu, base, sent));
+        pj[2 * u + 1] = gather<V4>(p4, off_index(w[u] >> 16, base, sent));
       }
       __builtin_amdgcn_sched_barrier(0);
       if (s + kPass < npl) la = nb4[(size_t)((s + kPass) / kGroup16) * stride];
       __builtin_amdgcn_sched_barrier(0);
-      body(pj);
+      body(pj, raw);
     }
     return;
   }
   int4 la = nb4[0], lb = nb4[stride];
   for (int s = 0; s < npl; s += kPass) {
+    raw[0] = la.x; raw[1] = la.y; raw[2] = la.z; raw[3] = la.w;
+    raw[4] = lb.x; raw[5] = lb.y; raw[6] = lb.z; raw[7] = lb.w;
     gather8(p4, la, lb, pj);
     __builtin_amdgcn_sched_barrier(0);
     if (s + kPass < npl) {
@@ -154,7 +170,37 @@ __device__ __forceinline__ void pair_passes(const V4 *p4, const int4 *nb4, int64
       lb = nb4[(size_t)((s + kPass) / kGroup + 1) * stride];
     }
     __builtin_amdgcn_sched_barrier(0);
-    body(pj);
+    body(pj, raw);
+  }
+}
+
+// Pruned lists.  The pruning density pass keeps, of every pass of the full
+// list, the entries within rin of the atom and writes them, in the order
+// they were met (pass, then slot, then lane), round-robin over the atom's
+// lanes: kept entry e goes to lane e % LPA, slot e / LPA, so the lanes of an
+// atom hold equal shares and the pruned list has the full list's layout.
+// cnt (equal in the atom's lanes) counts the kept entries so far.
+template <int LPA, bool L16>
+__device__ __forceinline__ void prune_put(const Params &p, int32_t *nbri, int64_t i, int lane, bool keep, int raw,
+                                          int &cnt) {
+  const int lb = (int)(threadIdx.x & 63) & ~(LPA - 1);
+  const unsigned long long bm = __ballot(keep);
+  const unsigned grp = (unsigned)(bm >> lb) & (unsigned)((1ull << LPA) - 1ull);
+  const int pos = cnt + __popc(grp & ((1u << lane) - 1u));
+  cnt += __popc(grp);
+  if (keep) {
+    if (L16) reinterpret_cast<uint16_t *>(nbri)[nbr16_index(i, pos, LPA, p.nbr_stride)] = (uint16_t)raw;
+    else nbri[nbr_index(i, pos, LPA, p.nbr_stride)] = raw;
+  }
+}
+
+// Sentinel entries after the cnt kept ones, up to whole passes of all lanes.
+template <int LPA, bool L16>
+__device__ __forceinline__ void prune_pad(const Params &p, int32_t *nbri, int64_t i, int lane, int cnt) {
+  const int padded = pass_slots<LPA>(cnt) * LPA;
+  for (int e = cnt + lane; e < padded; e += LPA) {
+    if (L16) reinterpret_cast<uint16_t *>(nbri)[nbr16_index(i, e, LPA, p.nbr_stride)] = (uint16_t)kOffSentinel;
+    else nbri[nbr_index(i, e, LPA, p.nbr_stride)] = (int)p.ntot;
   }
 }
 
@@ -266,6 +312,10 @@ __global__ void k_burst_begin(Buffers b, int n_rep, int64_t ntot) {
 
 __global__ void k_set_base(Control *ctl, int64_t base) { ctl->base = base; }
 __global__ void k_set_ncells(Control *ctl, int64_t n) { ctl->ncells = n; }
+__global__ void k_set_prune(Control *ctl, double rin2, double vb2) {
+  ctl->rin2 = rin2;
+  ctl->vb2 = vb2;
+}
 
 __global__ void k_fill_u64(unsigned long long *p, int64_t n, unsigned long long v) {
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
@@ -612,9 +662,9 @@ __device__ __forceinline__ void kick_atom(const Params &p, const Buffers &b, int
       if (gather) {
         // gather copy for the pair kernels; w (B') is rewritten by the density pass
         V4 v4;
-        v4.x = (R)a.x;
-        v4.y = (R)a.y;
-        v4.z = (R)a.z;
+        v4.x = (R)(a.x - gorigin<R>(rp, 0));
+        v4.y = (R)(a.y - gorigin<R>(rp, 1));
+        v4.z = (R)(a.z - gorigin<R>(rp, 2));
         v4.w = (R)0;
         reinterpret_cast<V4 *>(b.pos4)[i] = v4;
       }
@@ -633,6 +683,8 @@ __device__ __forceinline__ void kick_atom(const Params &p, const Buffers &b, int
       } else if (e2 > p.half_skin2) {
         set_err(b, E_SKIN);  // the lists this step will use are no longer valid
       }
+      // pruned lists: no atom may outrun the speed they were pruned for
+      if (p.inner && a.vx * a.vx + a.vy * a.vy + a.vz * a.vz > b.ctl->vb2) set_err(b, E_PRUNE);
       if (p.msum) {  // Eq. (mean_pos): this step's positions are sample s's
         b.msx[i] += a.x;
         b.msy[i] += a.y;
@@ -659,9 +711,9 @@ __device__ __forceinline__ void kick_atom(const Params &p, const Buffers &b, int
 // (lp = 1 would be off by |lambda - 1| dt |v|, up to 1e-4 A early in a
 // burst, where T is far from T0.)
 template <class R>
-__device__ __forceinline__ typename V4T<R>::T next_position(const Params &p, uint8_t g, double lp, double x, double y,
-                                                            double z, double vx, double vy, double vz, double fx,
-                                                            double fy, double fz) {
+__device__ __forceinline__ typename V4T<R>::T next_position(const Params &p, const RepInfo &rp, uint8_t g, double lp,
+                                                            double x, double y, double z, double vx, double vy,
+                                                            double vz, double fx, double fy, double fz) {
   typename V4T<R>::T n;
   if (moves_z(p, g)) {
     if (g != 0) fx = fy = 0.0;
@@ -669,9 +721,9 @@ __device__ __forceinline__ typename V4T<R>::T next_position(const Params &p, uin
     y += p.dt * (lp * vy + p.hdt_m * fy);
     z += p.dt * (lp * vz + p.hdt_m * fz);
   }
-  n.x = (R)x;
-  n.y = (R)y;
-  n.z = (R)z;
+  n.x = (R)(x - gorigin<R>(rp, 0));
+  n.y = (R)(y - gorigin<R>(rp, 1));
+  n.z = (R)(z - gorigin<R>(rp, 2));
   n.w = (R)0;
   return n;
 }
@@ -709,15 +761,16 @@ __global__ __launch_bounds__(kBlock) void k_pos4(Params p, Buffers b) {
   V4 *p4 = reinterpret_cast<V4 *>(b.pos4);
   V4 v = p4[i];
   const double x = b.x[i], y = b.y[i], z = b.z[i];
-  v.x = (R)x;
-  v.y = (R)y;
-  v.z = (R)z;
+  const int r = b.blk_rep[i / kTile];
+  const RepInfo &rp = b.rep[r];
+  v.x = (R)(x - gorigin<R>(rp, 0));
+  v.y = (R)(y - gorigin<R>(rp, 1));
+  v.z = (R)(z - gorigin<R>(rp, 2));
   p4[i] = v;
   if (p.fold) {
     // between the chunks of a burst: the same prediction the last force pass used
-    const int r = b.blk_rep[i / kTile];
-    reinterpret_cast<V4 *>(b.pnext)[i] =
-        next_position<R>(p, g, b.acc[r].lam_last, x, y, z, b.vx[i], b.vy[i], b.vz[i], b.fx[i], b.fy[i], b.fz[i]);
+    reinterpret_cast<V4 *>(b.pnext)[i] = next_position<R>(p, rp, g, b.acc[r].lam_last, x, y, z, b.vx[i], b.vy[i],
+                                                          b.vz[i], b.fx[i], b.fy[i], b.fz[i]);
   }
 }
 
@@ -758,7 +811,9 @@ __device__ void build_one(const Params &p, const Buffers &b, int64_t i, int lane
   const V4 *p4 = reinterpret_cast<const V4 *>(b.pos4);
   const RepInfo &rp = b.rep[r];
   const double xi = b.x[i], yi = b.y[i], zi = b.z[i];
-  const float4 pi = make_float4((float)xi, (float)yi, (float)zi, 0.f);
+  // in the gather copies' coordinates (the FP32 prefilter)
+  const float4 pi = make_float4((float)(R)(xi - gorigin<R>(rp, 0)), (float)(R)(yi - gorigin<R>(rp, 1)),
+                                (float)(R)(zi - gorigin<R>(rp, 2)), 0.f);
   if (lane == 0) {
     const double ex = xi - (double)b.xs[i], ey = yi - (double)b.ys[i], ez = zi - (double)b.zs[i];
     if (ex * ex + ey * ey + ez * ez > p.margin2) set_err(b, E_DRIFT);
@@ -810,6 +865,10 @@ __device__ void build_one(const Params &p, const Buffers &b, int64_t i, int lane
   const size_t group_stride = (size_t)p.nbr_stride * kGroup;
   int cnt = 0;
   bool wide = false;  // an offset beyond 16 bits met (reported once per atom below)
+  // 16-bit form: offsets count from the first index kept, which is the
+  // smallest (rows are met in increasing sorted order, and each row's atoms
+  // in order)
+  int base = -1;
   for (int q = 0; q < 25; ++q) {
     const int src = gbase + (q % KB);
     int rq = rs[0], eq = re[0];
@@ -840,16 +899,18 @@ __device__ void build_one(const Params &p, const Buffers &b, int64_t i, int lane
         if (ok && !(d2 < p.rlist2_lo))
           ok = dist2_plain(sub_plain(b.x[j], xi), sub_plain(b.y[j], yi), sub_plain(b.z[j], zi)) < p.rlist2;
         const unsigned long long m = (__ballot(ok) >> gbase) & gmask;
+        // (uniform over the atom's lanes; the source lane is one of them)
+        if (L16 && base < 0 && m != 0) base = __shfl(j, gbase + __ffsll((long long)m) - 1);
         const unsigned pos = (unsigned)cnt + (unsigned)__popcll(m & below);
         if (ok && pos < (unsigned)cap) {
           const unsigned l = pos % LPA, sl = pos / LPA;
           if (L16) {
-            const int d = j - self;
-            const bool fits = d >= -32767 && d <= 32767;
+            const int d = j - base;
+            const bool fits = d >= 0 && d < kOffSentinel;
             wide |= !fits;
-            reinterpret_cast<int16_t *>(b.nbr)[(size_t)(sl / kGroup16) * (size_t)p.nbr_stride * kGroup16 +
-                                               (size_t)self * (LPA * kGroup16) + l * kGroup16 + sl % kGroup16] =
-                (int16_t)(fits ? d : kOffSentinel);
+            reinterpret_cast<uint16_t *>(b.nbr)[(size_t)(sl / kGroup16) * (size_t)p.nbr_stride * kGroup16 +
+                                                (size_t)self * (LPA * kGroup16) + l * kGroup16 + sl % kGroup16] =
+                (uint16_t)(fits ? d : kOffSentinel);
           } else {
             b.nbr[(size_t)(sl / kGroup) * group_stride + slot_base + l * kGroup + sl % kGroup] = j;
           }
@@ -864,12 +925,13 @@ __device__ void build_one(const Params &p, const Buffers &b, int64_t i, int lane
   // pad to whole passes with the sentinel (cap is a multiple of kPass * LPA)
   const int padded = (cnt + kPass * LPA - 1) / (kPass * LPA) * (kPass * LPA);
   for (int e = cnt + lane; e < padded; e += KB) {
-    if (L16) reinterpret_cast<int16_t *>(b.nbr)[nbr16_index(i, e, LPA, p.nbr_stride)] = (int16_t)kOffSentinel;
+    if (L16) reinterpret_cast<uint16_t *>(b.nbr)[nbr16_index(i, e, LPA, p.nbr_stride)] = (uint16_t)kOffSentinel;
     else b.nbr[nbr_index(i, e, LPA, p.nbr_stride)] = (int)p.ntot;
   }
   if (lane == 0) {
     if (over) set_err(b, E_OVERFLOW);
     b.ncount[i] = cnt;
+    if (L16) b.nbase[i] = base < 0 ? self : base;
     b.xr[i] = (float)xi;
     b.yr[i] = (float)yi;
     b.zr[i] = (float)zi;
@@ -901,7 +963,10 @@ __global__ __launch_bounds__(kBlock) void k_build(Params p, Buffers b, int32_t c
 // update it exactly (lane 0 stores, the gather copy with its B').  One
 // kernel boundary less per step.  Step 0 (forces at a burst's start) is
 // the plain density pass.
-template <class R, int LPA, int NM, bool L16>
+// PR: a pruning pass (Params::inner): it walks the full list and writes the
+// pruned one (the entries within rin, Control::rin2), which the pair passes
+// of the following steps, up to the next pruning pass, read instead.
+template <class R, int LPA, int NM, bool L16, bool PR>
 __global__ __launch_bounds__(kBlock) void k_density(Params p, Buffers b, int32_t k) {
   using V4 = typename V4T<R>::T;
   const int64_t gt = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -944,15 +1009,21 @@ __global__ __launch_bounds__(kBlock) void k_density(Params p, Buffers b, int32_t
   int np = 0;
   if (real) {
     const R rc2 = (R)p.rc2, a = (R)p.a;
+    // the full list when pruning (or without pruned lists), else the pruned one
+    const bool full = PR || !p.inner;
     // slots per lane: the list is padded with the far-away sentinel to whole
     // passes, so every slot of a pass holds a valid index
-    const int npl = pass_slots<LPA>(b.ncount[i]);
-    const int4 *nb4 = reinterpret_cast<const int4 *>(b.nbr) + (size_t)i * LPA + lane;
-    pair_passes<L16>(pn, nb4, p.nbr_stride, npl, (int)i, (int)p.ntot, [&](const V4(&pj)[8]) {
+    const int npl = pass_slots<LPA>((full ? b.ncount : b.ncounti)[i]);
+    const int base = L16 ? b.nbase[i] : 0;
+    const int4 *nb4 = reinterpret_cast<const int4 *>(full ? b.nbr : b.nbri) + (size_t)i * LPA + lane;
+    const R rin2 = PR ? (R)b.ctl->rin2 : (R)0;
+    int kept = 0;
+    pair_passes<L16>(pn, nb4, p.nbr_stride, npl, base, (int)p.ntot, [&](const V4(&pj)[8], const int(&raw)[8]) {
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const R dx = pj[u].x - pi.x, dy = pj[u].y - pi.y, dz = pj[u].z - pi.z;
         const R r2 = dx * dx + dy * dy + dz * dz;
+        if (PR) prune_put<LPA, L16>(p, b.nbri, i, lane, r2 < rin2, raw[u], kept);
         if (r2 < rc2) {
           const R rinv = rsqrt_r(r2);
           if (NM == 2) {
@@ -968,6 +1039,10 @@ __global__ __launch_bounds__(kBlock) void k_density(Params p, Buffers b, int32_t
         }
       }
     });
+    if (PR) {
+      prune_pad<LPA, L16>(p, b.nbri, i, lane, kept);
+      if (lane == 0) b.ncounti[i] = kept;
+    }
   }
 #pragma unroll
   for (int o = LPA / 2; o > 0; o >>= 1) {
@@ -985,9 +1060,9 @@ __global__ __launch_bounds__(kBlock) void k_density(Params p, Buffers b, int32_t
     // state after lambda (no drift); the rest of this step is not needed
     kick_atom<R>(p, b, i, at, st.lam, !st.stop, false, *st.rep, lane == 0, false);
     if (st.stop) return;
-    pi.x = (R)at.x;
-    pi.y = (R)at.y;
-    pi.z = (R)at.z;
+    pi.x = (R)(at.x - gorigin<R>(*st.rep, 0));
+    pi.y = (R)(at.y - gorigin<R>(*st.rep, 1));
+    pi.z = (R)(at.z - gorigin<R>(*st.rep, 2));
   }
   long long q[1] = {0};
   if (lane == 0 && real) {
@@ -1056,10 +1131,13 @@ __global__ __launch_bounds__(kBlock) void k_force(Params p, Buffers b, int32_t k
     }
   }
   const double eshift = (NM != 2 && real && lane == 0) ? b.eshift[i] : 0.0;  // read ahead too
+  const double zc = b.rep[r].center[2];
   const V4 *p4 = reinterpret_cast<const V4 *>(b.pos4);
   // The virial W_zz = 1/2 sum_ij (z_i - z_j) F_ij,z equals sum_i z_i F_i,z
   // for these pair-antisymmetric internal forces, so it is formed per atom
-  // after the loop instead of per pair.
+  // after the loop instead of per pair; and since they sum to zero, as
+  // sum_i (z_i - z_c) F_i,z about the cube's centre z_c, which weights each
+  // force's rounding by at most the cube's half height.
   // Sutton-Chen, with w_j = -m B'_j from the density pass:
   //   dU/dr = [-n eps (a/r)^n + (w_i + w_j) (a/r)^m] / r - (dVc - (w_i + w_j) drhoc / m)
   // and the pair energy V - Vc - (r - rc) dVc summed as sum(-n V) here and
@@ -1073,9 +1151,10 @@ __global__ __launch_bounds__(kBlock) void k_force(Params p, Buffers b, int32_t k
     const R dVc = (R)p.dVc, dm = (R)(p.drhoc / p.m);
     // slots per lane: the list is padded with the far-away sentinel to whole
     // passes, so every slot of a pass holds a valid index
-    const int npl = pass_slots<LPA>(b.ncount[i]);
-    const int4 *nb4 = reinterpret_cast<const int4 *>(b.nbr) + (size_t)i * LPA + lane;
-    pair_passes<L16>(p4, nb4, p.nbr_stride, npl, (int)i, (int)p.ntot, [&](const V4(&pj)[8]) {
+    const int npl = pass_slots<LPA>((p.inner ? b.ncounti : b.ncount)[i]);
+    const int base = L16 ? b.nbase[i] : 0;
+    const int4 *nb4 = reinterpret_cast<const int4 *>(p.inner ? b.nbri : b.nbr) + (size_t)i * LPA + lane;
+    pair_passes<L16>(p4, nb4, p.nbr_stride, npl, base, (int)p.ntot, [&](const V4(&pj)[8], const int(&)[8]) {
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const R dx = pj[u].x - pi.x, dy = pj[u].y - pi.y, dz = pj[u].z - pi.z;
@@ -1152,7 +1231,7 @@ __global__ __launch_bounds__(kBlock) void k_force(Params p, Buffers b, int32_t k
       // before a rebuild point, whether the lists last until the one after
       // it (from here, over m steps)
       const double lp = mode == 1 ? 1.0 : b.acc[r].lam_last;
-      reinterpret_cast<V4 *>(b.pnext)[i] = next_position<R>(p, g, lp, x, y, z, vx, vy, vz, Fx, Fy, Fz);
+      reinterpret_cast<V4 *>(b.pnext)[i] = next_position<R>(p, b.rep[r], g, lp, x, y, z, vx, vy, vz, Fx, Fy, Fz);
       if (mode == 2 && moves_z(p, g)) {
         const double ex = x - (double)b.xr[i], ey = y - (double)b.yr[i], ez = z - (double)b.zr[i];
         if (sqrt(ex * ex + ey * ey + ez * ez) + p.trig_v * sqrt(vx * vx + vy * vy + vz * vz) > p.trig_lim)
@@ -1162,7 +1241,7 @@ __global__ __launch_bounds__(kBlock) void k_force(Params p, Buffers b, int32_t k
     // pair energy of the atom: tables sum V; Sutton-Chen sums -n V, plus the shift
     const double epair = (NM == 2) ? (double)ep : -(double)ep / p.n + eshift;
     q[Q_EPAIR] = to_fix(0.5 * epair);
-    q[Q_WZZ] = to_fix(z * Fz);
+    q[Q_WZZ] = to_fix((z - zc) * Fz);
     if (g == 2) q[Q_RZ] = to_fix(-Fz);
   }
   block_atoms_add<kNQ, kBlock / LPA>(q, lane == 0, threadIdx.x / LPA,
@@ -1519,10 +1598,11 @@ __global__ __launch_bounds__(kBlock) void k_permute(Buffers b, Buffers sc, const
   sc.xs[i] = (float)x;
   sc.ys[i] = (float)y;
   sc.zs[i] = (float)z;
+  const RepInfo &rp = b.rep[b.blk_rep[i / kTile]];
   V4 v;
-  v.x = (R)x;
-  v.y = (R)y;
-  v.z = (R)z;
+  v.x = (R)(x - gorigin<R>(rp, 0));
+  v.y = (R)(y - gorigin<R>(rp, 1));
+  v.z = (R)(z - gorigin<R>(rp, 2));
   v.w = (R)0;
   reinterpret_cast<V4 *>(sc.pos4)[i] = v;
 }
@@ -1597,19 +1677,20 @@ __global__ __launch_bounds__(kBlock) void k_strain(Params p, Buffers b, const do
   b.z[i] = b.z[i] * factor[r];
 }
 
-// pairs within rc (directed) and list entries, summed into stat[r][slot][0..1]
+// pairs within rc (directed), list entries and pruned-list entries, summed into stat[r][slot][0..2]
 template <class R>
 __global__ __launch_bounds__(kBlock) void k_count_pairs(Params p, Buffers b) {
   const int64_t tile = blockIdx.x;
   const int r = b.blk_rep[tile];
   const int64_t i = tile * kTile + threadIdx.x;
-  unsigned long long np = 0, ne = 0;
+  unsigned long long np = 0, ne = 0, nq = 0;
   if (b.group[i] != kPad) {
     const int cnt = b.ncount[i];
     ne = cnt;
+    nq = p.inner ? (unsigned long long)b.ncounti[i] : 0ull;
     for (int e = 0; e < cnt; ++e) {
-      const int j = p.list16 ? off_index(reinterpret_cast<const int16_t *>(b.nbr)[nbr16_index(i, e, p.lpa, p.nbr_stride)],
-                                       (int)i, (int)p.ntot)
+      const int j = p.list16 ? off_index(reinterpret_cast<const uint16_t *>(b.nbr)[nbr16_index(i, e, p.lpa, p.nbr_stride)],
+                                       b.nbase[i], (int)p.ntot)
                            : b.nbr[nbr_index(i, e, p.lpa, p.nbr_stride)];
       const double d2 = dist2_plain(b.x[j] - b.x[i], b.y[j] - b.y[i], b.z[j] - b.z[i]);
       if (d2 < p.rc2) ++np;
@@ -1618,11 +1699,13 @@ __global__ __launch_bounds__(kBlock) void k_count_pairs(Params p, Buffers b) {
   for (int o = 32; o > 0; o >>= 1) {
     np += (unsigned long long)shfl_xor_ll((long long)np, o);
     ne += (unsigned long long)shfl_xor_ll((long long)ne, o);
+    nq += (unsigned long long)shfl_xor_ll((long long)nq, o);
   }
   if ((threadIdx.x & 63) == 0) {
     unsigned long long *row = b.stat + ((size_t)r * kSlots + (blockIdx.x & (kSlots - 1))) * kStat;
     atomicAdd(row, np);
     atomicAdd(row + 1, ne);
+    atomicAdd(row + 2, nq);
   }
 }
 
@@ -1643,6 +1726,10 @@ void launch_set_ncells(const Buffers &b, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_set_ncells, dim3(1), dim3(1), 0, s, b.ctl, n);
 }
 
+void launch_set_prune(const Buffers &b, double rin2, double vb2, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_prune, dim3(1), dim3(1), 0, s, b.ctl, rin2, vb2);
+}
+
 void launch_fill_i64(unsigned long long *ptr, int64_t n, unsigned long long v, hipStream_t s) {
   if (n <= 0) return;
   unsigned g = (unsigned)std::min<int64_t>((n + kBlock - 1) / kBlock, 1024);
@@ -1659,16 +1746,22 @@ void launch_pos4(const Params &p, const Buffers &b, int precision, hipStream_t s
   else hipLaunchKernelGGL(k_pos4<double>, dim3(tiles(p)), dim3(kBlock), 0, s, p, b);
 }
 
-template <class R, int NM, bool L16>
+template <class R, int NM, bool L16, bool PR>
 static void density_lpa(const Params &p, const Buffers &b, int lpa, int32_t k, hipStream_t s) {
   const unsigned g = (unsigned)(p.ntot * lpa / kBlock);
   switch (lpa) {
-    case 1: hipLaunchKernelGGL((k_density<R, 1, NM, L16>), dim3(g), dim3(kBlock), 0, s, p, b, k); break;
-    case 2: hipLaunchKernelGGL((k_density<R, 2, NM, L16>), dim3(g), dim3(kBlock), 0, s, p, b, k); break;
-    case 4: hipLaunchKernelGGL((k_density<R, 4, NM, L16>), dim3(g), dim3(kBlock), 0, s, p, b, k); break;
-    case 8: hipLaunchKernelGGL((k_density<R, 8, NM, L16>), dim3(g), dim3(kBlock), 0, s, p, b, k); break;
-    default: hipLaunchKernelGGL((k_density<R, 16, NM, L16>), dim3(g), dim3(kBlock), 0, s, p, b, k); break;
+    case 1: hipLaunchKernelGGL((k_density<R, 1, NM, L16, PR>), dim3(g), dim3(kBlock), 0, s, p, b, k); break;
+    case 2: hipLaunchKernelGGL((k_density<R, 2, NM, L16, PR>), dim3(g), dim3(kBlock), 0, s, p, b, k); break;
+    case 4: hipLaunchKernelGGL((k_density<R, 4, NM, L16, PR>), dim3(g), dim3(kBlock), 0, s, p, b, k); break;
+    case 8: hipLaunchKernelGGL((k_density<R, 8, NM, L16, PR>), dim3(g), dim3(kBlock), 0, s, p, b, k); break;
+    default: hipLaunchKernelGGL((k_density<R, 16, NM, L16, PR>), dim3(g), dim3(kBlock), 0, s, p, b, k); break;
   }
+}
+
+template <class R, int NM>
+static void density_form(const Params &p, const Buffers &b, int lpa, int32_t k, hipStream_t s, bool prune) {
+  if (p.list16) (prune ? density_lpa<R, NM, true, true> : density_lpa<R, NM, true, false>)(p, b, lpa, k, s);
+  else (prune ? density_lpa<R, NM, false, true> : density_lpa<R, NM, false, false>)(p, b, lpa, k, s);
 }
 
 template <class R, int NM, bool L16>
@@ -1704,14 +1797,16 @@ void launch_build(const Params &p, const Buffers &b, int precision, int lpa, hip
   else (p.list16 ? build_lpa<double, true> : build_lpa<double, false>)(p, b, lpa, cond, s);
 }
 
-void launch_density(const Params &p, const Buffers &b, int precision, int lpa, int32_t k, hipStream_t s) {
+void launch_density(const Params &p, const Buffers &b, int precision, int lpa, int32_t k, hipStream_t s,
+                    bool prune) {
+  prune = prune && p.inner;
   switch (pot_form(p) + 3 * (precision ? 1 : 0)) {
-    case 0: (p.list16 ? density_lpa<double, 0, true> : density_lpa<double, 0, false>)(p, b, lpa, k, s); break;
-    case 1: (p.list16 ? density_lpa<double, 1, true> : density_lpa<double, 1, false>)(p, b, lpa, k, s); break;
-    case 2: (p.list16 ? density_lpa<double, 2, true> : density_lpa<double, 2, false>)(p, b, lpa, k, s); break;
-    case 3: (p.list16 ? density_lpa<float, 0, true> : density_lpa<float, 0, false>)(p, b, lpa, k, s); break;
-    case 4: (p.list16 ? density_lpa<float, 1, true> : density_lpa<float, 1, false>)(p, b, lpa, k, s); break;
-    default: (p.list16 ? density_lpa<float, 2, true> : density_lpa<float, 2, false>)(p, b, lpa, k, s); break;
+    case 0: density_form<double, 0>(p, b, lpa, k, s, prune); break;
+    case 1: density_form<double, 1>(p, b, lpa, k, s, prune); break;
+    case 2: density_form<double, 2>(p, b, lpa, k, s, prune); break;
+    case 3: density_form<float, 0>(p, b, lpa, k, s, prune); break;
+    case 4: density_form<float, 1>(p, b, lpa, k, s, prune); break;
+    default: density_form<float, 2>(p, b, lpa, k, s, prune); break;
   }
 }
 

@@ -35,7 +35,8 @@ enum : int {
   E_DRIFT = 8,     // an atom drifted beyond the binning margin before a list build
   E_STATE = 16,    // thermostat: T <= 0 or lambda^2 < 0
   E_SKIN = 32,     // an atom moved more than half the skin since the list build (a trigger was missed)
-  E_WIDE = 64      // a list entry's offset does not fit the 16-bit list form
+  E_WIDE = 64,     // a list entry's offset does not fit the 16-bit list form
+  E_PRUNE = 128    // an atom moved faster than the pruned lists allow (Control::vb2)
 };
 
 // Device-resident control block (one per system).
@@ -52,6 +53,11 @@ struct Control {
   double conv_floor[4];   // lower bound of the error's denominator (0: the plain relative error)
   int64_t nbuild;         // list builds triggered on the device (running count)
   uint64_t kt_first, kt_last;  // earliest start and latest end stamp of the last timed force launch
+  // pruned lists (Params::inner): a pruning density pass keeps the entries
+  // within rin of the atom; every kick checks |v|^2 <= vb2, which keeps each
+  // atom within (rin - rc)/2 of where it was at the last pruning pass
+  double rin2;
+  double vb2;
 };
 
 constexpr int kStat = 16;  // u64 entries per statistics row
@@ -127,6 +133,8 @@ struct Params {
   int32_t tab_nrho;
   int32_t fold;        // nonzero (mixed form): the density pass does the step's kick-drift (Buffers::pnext)
   int32_t list16;      // nonzero: the Verlet lists hold 16-bit offsets (nbr16_index), else 32-bit indices
+  int32_t inner;       // nonzero: the pair passes read the pruned lists (nbri, ncounti), which the
+                       // density pass of each pruning step writes from the full ones
 };
 
 // Device buffers (pointers), passed by value.
@@ -141,6 +149,9 @@ struct Buffers {
   float *xr, *yr, *zr; // positions at the last list build
   int32_t *nbr;        // Verlet lists, [slot][atom*lpa + lane] (32-bit indices or 16-bit offsets, Params::list16)
   int32_t *ncount;     // list length per atom
+  int32_t *nbase;      // 16-bit form: the index the atom's offsets count from (its smallest listed neighbour)
+  int32_t *nbri;       // pruned lists (same layout and entry form as nbr)
+  int32_t *ncounti;    // pruned list length per atom
   double *eshift;      // Sutton-Chen: the pair-energy shift -n_c Vc - dVc (sum r - n_c rc) over the atom's
                        // pairs within rc, from the density pass (which sums r and n_c for rho's shift)
   int32_t *cell_start; // global cell arrays: [cell_off + c]
@@ -173,14 +184,17 @@ __host__ __device__ inline size_t nbr_index(int64_t i, int e, int lpa, int64_t s
   return ((size_t)(s / kGroup) * (size_t)stride + (size_t)i * lpa + l) * kGroup + (s % kGroup);
 }
 
-// The 16-bit form of the lists: entry e of atom i holds the offset j - i
-// (sorted order keeps an atom's neighbours within a few bin layers of it),
-// eight to a group per lane, so one 16-byte load gives a lane a whole pass
-// and the pair kernels read half the list bytes.  kOffSentinel stands for
-// the sentinel index ntot.  A system whose offsets outgrow 16 bits (a build
+// The 16-bit form of the lists: entry e of atom i holds the unsigned offset
+// j - nbase[i], where nbase[i] is the smallest index in the atom's list
+// (sorted order keeps an atom's neighbours within a few bin layers of it:
+// with bins of edge h, those within rlist of it span less than
+// 2 rlist + h of z, about 50,000 atoms of a 500,000-atom cube), eight to a
+// group per lane, so one 16-byte load gives a lane a whole pass and the
+// pair kernels read half the list bytes.  kOffSentinel stands for the
+// sentinel index ntot.  A system whose offsets outgrow 16 bits (a build
 // meets one: E_WIDE) switches to the 32-bit form for good.
 constexpr int kGroup16 = 8;
-constexpr int kOffSentinel = -32768;
+constexpr int kOffSentinel = 0xffff;
 __host__ __device__ inline size_t nbr16_index(int64_t i, int e, int lpa, int64_t stride) {
   const int l = e % lpa, s = e / lpa;
   return ((size_t)(s / kGroup16) * (size_t)stride + (size_t)i * lpa + l) * kGroup16 + (s % kGroup16);
@@ -192,11 +206,13 @@ void launch_hold_group(const Buffers &b, int64_t ntot, int g, hipStream_t s);
 void launch_kick_drift(const Params &p, const Buffers &b, int precision, int32_t k, int32_t mode, hipStream_t s);
 void launch_pos4(const Params &p, const Buffers &b, int precision, hipStream_t s);
 void launch_build(const Params &p, const Buffers &b, int precision, int lpa, hipStream_t s, int32_t cond = 0);
-void launch_density(const Params &p, const Buffers &b, int precision, int lpa, int32_t k, hipStream_t s);
+void launch_density(const Params &p, const Buffers &b, int precision, int lpa, int32_t k, hipStream_t s,
+                    bool prune = false);
 void launch_force(const Params &p, const Buffers &b, int precision, int lpa, int32_t k, int32_t mode,
                   hipStream_t s);
 void launch_set_base(const Buffers &b, int64_t base, hipStream_t s);
 void launch_set_ncells(const Buffers &b, int64_t n, hipStream_t s);
+void launch_set_prune(const Buffers &b, double rin2, double vb2, hipStream_t s);
 void launch_chunk_stats(const Params &p, const Buffers &b, hipStream_t s, int64_t n_stamps = 0);
 void launch_snapshot(const Buffers &b, double *snap, unsigned long long *snap_slots, double *snap_acc, int restore,
                      int64_t ntot, int64_t nslots, int64_t nacc, hipStream_t s);

@@ -114,12 +114,15 @@ struct ptamd_system {
   bool timing = false;
   double t_ev_ms = 0.0;   // the same launches bracketed by HIP events (includes dispatch latency)
   double wall_khz = 1e5;  // device wall-clock rate
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
+  double t_den_ms = 0.0;  // density launches bracketed by HIP events
   double t_sum_ms = 0.0;
   int64_t t_count = 0;
   int chunk = 64;
   int64_t steps_total = 0, sorts = 0, rollbacks = 0, list_builds = 0;
   int64_t nbuild_seen = 0;  // device-side builds already counted in list_builds
+  bool prune = true;        // pruned lists between pruning passes (ptamd_md_params::full_lists == 0)
+  double rin = 0.0;         // radius of the last chunk's pruned lists (0: full lists)
   int64_t series_rows = 0;
 };
 
@@ -211,6 +214,8 @@ static void alloc_buffers(Buffers &b, int64_t ntot, int precision, bool primary)
   if (primary) {
     b.xr = dalloc<float>(ntot); b.yr = dalloc<float>(ntot); b.zr = dalloc<float>(ntot);
     b.ncount = dalloc<int32_t>(ntot);
+    b.nbase = dalloc<int32_t>(ntot);
+    b.ncounti = dalloc<int32_t>(ntot);
     b.eshift = dalloc<double>(ntot);
     if (precision && ntot <= kFoldMaxAtoms) b.pnext = dalloc<float4>(ntot + 1);  // with the sentinel, as pos4
   }
@@ -218,7 +223,7 @@ static void alloc_buffers(Buffers &b, int64_t ntot, int precision, bool primary)
 
 static void free_buffers(Buffers &b) {
   void *ptrs[] = {b.x, b.y, b.z, b.vx, b.vy, b.vz, b.fx, b.fy, b.fz, b.pos4, b.pnext, b.group, b.orig, b.cell,
-                  b.xs, b.ys, b.zs, b.xr, b.yr, b.zr, b.nbr, b.ncount, b.eshift, b.cell_start, b.cell_count,
+                  b.xs, b.ys, b.zs, b.xr, b.yr, b.zr, b.nbr, b.ncount, b.nbase, b.nbri, b.ncounti, b.eshift, b.cell_start, b.cell_count,
                   b.blk_rep, b.rep, b.acc, b.slots, b.stat, b.series, b.ktime, b.msx, b.msy, b.msz,
                   b.tab_r, b.tab_F};
   for (void *p : ptrs) dfree(p);
@@ -256,9 +261,12 @@ static void alloc_list(ptamd_system *s, int cap) {
   const int q = s->lpa * kPass;  // lists are padded to whole passes of every lane
   cap = (cap + q - 1) / q * q;
   dfree(s->B.nbr);
-  s->B.nbr = nullptr;
-  // 16-bit form: two entries per 32-bit word
+  dfree(s->B.nbri);
+  s->B.nbr = s->B.nbri = nullptr;
+  // 16-bit form: two entries per 32-bit word; the pruned lists have the
+  // same layout and capacity
   s->B.nbr = dalloc<int32_t>((size_t)s->ntot * cap / (s->P.list16 ? 2 : 1));
+  s->B.nbri = dalloc<int32_t>((size_t)s->ntot * cap / (s->P.list16 ? 2 : 1));
   s->cap = cap;
   s->P.cap_slots = cap / s->lpa;
   invalidate_graphs(s);
@@ -313,11 +321,13 @@ static ptamd_system *create_from_hosts(const std::vector<HostState> &hs, const s
     s->precision = md.precision;
     s->sc = sc;
     s->md = md;
+    s->prune = md.full_lists == 0;
     s->skin = md.skin;
     s->margin = 2.0;
     HIPCHK(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
     HIPCHK(hipEventCreate(&s->ev0));
     HIPCHK(hipEventCreate(&s->ev1));
+    HIPCHK(hipEventCreate(&s->ev2));
     {
       int khz = 0;
       HIPCHK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, s->device));
@@ -472,6 +482,7 @@ static ptamd_system *create_from_hosts(const std::vector<HostState> &hs, const s
     if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
     if (s->ev0) (void)hipEventDestroy(s->ev0);
     if (s->ev1) (void)hipEventDestroy(s->ev1);
+  if (s->ev2) (void)hipEventDestroy(s->ev2);
     delete s;
     throw;
   }
@@ -587,8 +598,8 @@ static void sort_system(ptamd_system *s) {
 // valid inside the graph without a return to the host.
 static GraphEntry &get_graph(ptamd_system *s, int K, bool with_build, int m) {
   // every launch-time flag captured in the graph is part of its key
-  const int key = 32 * K + (m > 1 ? 16 : 0) + (s->P.msum ? 8 : 0) + (s->P.top_free ? 4 : 0) + (s->P.conv ? 2 : 0) +
-                  (with_build ? 1 : 0);
+  const int key = 64 * K + (s->P.inner ? 32 : 0) + (m > 1 ? 16 : 0) + (s->P.msum ? 8 : 0) + (s->P.top_free ? 4 : 0) +
+                  (s->P.conv ? 2 : 0) + (with_build ? 1 : 0);
   auto it = s->graphs.find(key);
   if (it != s->graphs.end()) return it->second;
   GraphEntry g;
@@ -599,17 +610,21 @@ static GraphEntry &get_graph(ptamd_system *s, int K, bool with_build, int m) {
   const bool fold = s->P.fold != 0;
   s->P.trig_v = (fold ? m : m - 1) * 1.5 * s->md.dt_fs;
   HIPCHK(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
+  // with pruned lists (Params::inner, only where m > 1) the density passes
+  // of the first step and of every rebuild point prune: a pruned list serves
+  // at most m steps, over which no atom drifts more than m - 1 steps' worth
   if (with_build) launch_build(s->P, s->B, s->precision, s->lpa, s->cap_stream);
   for (int32_t k = 0; k < K; ++k) {
     const bool point = k % m == m - 1;
+    const bool prune = k == 0 || point;
     if (fold) {
       if (point) launch_build(s->P, s->B, s->precision, s->lpa, s->cap_stream, 1);
-      launch_density(s->P, s->B, s->precision, s->lpa, k, s->cap_stream);
+      launch_density(s->P, s->B, s->precision, s->lpa, k, s->cap_stream, prune);
       launch_force(s->P, s->B, s->precision, s->lpa, k, (k + 1) % m == m - 1 ? 2 : 0, s->cap_stream);
     } else {
       launch_kick_drift(s->P, s->B, s->precision, k, point ? 2 : 0, s->cap_stream);
       if (point) launch_build(s->P, s->B, s->precision, s->lpa, s->cap_stream, 1);
-      launch_density(s->P, s->B, s->precision, s->lpa, k, s->cap_stream);
+      launch_density(s->P, s->B, s->precision, s->lpa, k, s->cap_stream, prune);
       launch_force(s->P, s->B, s->precision, s->lpa, k, 0, s->cap_stream);
     }
   }
@@ -621,18 +636,19 @@ static GraphEntry &get_graph(ptamd_system *s, int K, bool with_build, int m) {
   return s->graphs[key] = g;
 }
 
-// Graph length of a chunk of K steps (the first of which is launched
-// directly when the force kernel is timed): 1..15, then multiples of 8, so
+// Graph length of a chunk of K steps (the first nd of which are launched
+// directly when the pair kernels are timed): 1..15, then multiples of 8, so
 // that the drift-bounded chunk lengths, which vary from chunk to chunk, need
 // at most 46 graphs (each new one costs a capture and an instantiation).
-static int chunk_graph_steps(int K, bool timing) {
-  const int g = K - (timing ? 1 : 0);
+static int chunk_graph_steps(int K, int nd) {
+  const int g = K - nd;
   return g >= 16 ? g - g % 8 : g;
 }
 
 // Instantiates every chunk graph a fixed-length burst can launch with the
 // current launch configuration and flags (normal rebuild-point spacing).
 static void prepare_graphs(ptamd_system *s) {
+  s->P.inner = s->prune ? 1 : 0;
   for (int g = 1; g <= kMaxChunk; g += (g < 16 ? 1 : 8)) {
     get_graph(s, g, false, kRebuildEvery);
     if (!s->timing) get_graph(s, g, true, kRebuildEvery);
@@ -706,9 +722,12 @@ static void initial_forces(ptamd_system *s) {
   if (s->need_sort) sort_system(s);
   launch_burst_begin(s->P, s->B, s->n_rep, s->stream);
   launch_set_base(s->B, 0, s->stream);
-  launch_build(s->P, s->B, s->precision, s->lpa, s->stream);
-  launch_density(s->P, s->B, s->precision, s->lpa, 0, s->stream);
-  launch_force(s->P, s->B, s->precision, s->lpa, 0, 1, s->stream);
+  // forces at the burst start from the full lists (the first chunk prunes)
+  Params P0 = s->P;
+  P0.inner = 0;
+  launch_build(P0, s->B, s->precision, s->lpa, s->stream);
+  launch_density(P0, s->B, s->precision, s->lpa, 0, s->stream);
+  launch_force(P0, s->B, s->precision, s->lpa, 0, 1, s->stream);
   check_launch();
   read_ctl(s);
   s->list_builds++;
@@ -779,6 +798,7 @@ static void run_burst(ptamd_system *s, int64_t n_steps, ptamd_averages *out, con
   int64_t step = 1;
   int chunk = kMaxChunk;  // the same schedule for every burst: results depend on the inputs only
   int retries = 0;        // roll-backs since the last completed chunk
+  double prune_room = 1.5;  // speed bound of the pruned lists, in units of the chunk's largest speed
   while (step <= n_steps) {
     // Inside a chunk the lists are rebuilt on the device (rebuild points
     // every m steps, see get_graph).  Per step an atom moves at most
@@ -796,7 +816,24 @@ static void run_burst(ptamd_system *s, int64_t n_steps, ptamd_averages *out, con
                               std::to_string(st.vmax) + " A/fs)");
     // fast atoms (hot systems): a rebuild point at every step
     const int m = (kRebuildEvery + 1) * vb <= skin_room ? kRebuildEvery : 1;
-    if (!s->need_build && st.ldisp + (m + 1) * vb > skin_room) s->need_build = true;
+    // Pruned lists, used where rebuild points are spaced: a pruning pass keeps
+    // the pairs within rin = rc + 2 (m - 1) dt vs of each other, with vs a
+    // bound on every atom's speed that each kick checks (E_PRUNE otherwise),
+    // so that no pair closer than rc at any step before the next pruning is
+    // left out.  2e-3 A covers the FP32 rounding of the coordinates and the
+    // predicted positions of the folded step.  The bound is at least
+    // 0.01 A/fs (a tenth of an Angstrom of room over four steps), so that a
+    // sample starting from rest does not outrun it as it accelerates.
+    {
+      const double vs = prune_room * std::max(st.vmax, 0.01 / 1.5);
+      const double rin = s->sc.rc + 2.0 * (m - 1) * s->md.dt_fs * vs + 2e-3;
+      s->P.inner = (m > 1 && s->prune && rin < s->sc.rc + 0.9 * s->skin) ? 1 : 0;
+      s->rin = s->P.inner ? rin : 0.0;
+      if (s->P.inner) launch_set_prune(s->B, rin * rin, vs * vs, s->stream);
+    }
+    // (timed chunks launch two steps before their graph, whose first rebuild
+    // point comes one step later)
+    if (!s->need_build && st.ldisp + (m + 1 + (timing ? 1 : 0)) * vb > skin_room) s->need_build = true;
     if (st.drift + kMinSortChunk * vb > drift_room) s->need_sort = true;
     if (s->need_sort) {
       sort_system(s);  // a new order: the lists are rebuilt
@@ -812,36 +849,45 @@ static void run_burst(ptamd_system *s, int64_t n_steps, ptamd_averages *out, con
       const int64_t c = std::max<int64_t>(2 * lag, (step - 1 + lag - 1) / lag * lag);
       if (c + 1 >= step) K = (int)std::min<int64_t>(K, c + 1 - step + 1);
     }
-    K = chunk_graph_steps(K, timing) + (timing ? 1 : 0);
+    const int nd = timing ? std::min(K, 2) : 0;  // steps launched directly
+    K = chunk_graph_steps(K, nd) + nd;
     snapshot(s, false);
     launch_set_base(s->B, step, s->stream);
     int done = 0;
     if (timing) {
-      // the chunk's first step is launched directly, its force kernel bracketed
-      // by events on the system's stream; the rest of the chunk is a graph
+      // The chunk's first two steps are launched directly, the rest of the
+      // chunk is a graph.  The first prunes the lists; the second, a step as
+      // most are, has its density and force kernels bracketed by events on
+      // the system's stream (and the force kernel stamps the device clock).
+      // (Mixed form: the graph's first rebuild point is chunk step nd + m - 1,
+      // whose trigger comes from the step before; with m = 1 from the last
+      // direct step.)
       if (build) launch_build(s->P, s->B, s->precision, s->lpa, s->stream);
-      if (!s->P.fold) launch_kick_drift(s->P, s->B, s->precision, 0, 0, s->stream);
-      launch_density(s->P, s->B, s->precision, s->lpa, 0, s->stream);
-      Params pt = s->P;
-      pt.ktime = 1;
-      HIPCHK(hipEventRecord(s->ev0, s->stream));
-      // (mixed form: the graph's first rebuild point is chunk step m, whose
-      // trigger comes from chunk step m - 1; with m = 1 from this one)
-      launch_force(pt, s->B, s->precision, s->lpa, 0, (s->P.fold && m == 1) ? 2 : 0, s->stream);
-      HIPCHK(hipEventRecord(s->ev1, s->stream));
-      done = 1;
-      if (K > 1) launch_set_base(s->B, step + 1, s->stream);
+      for (int k = 0; k < nd; ++k) {
+        const bool timed = k == nd - 1 && nd == 2;
+        if (!s->P.fold) launch_kick_drift(s->P, s->B, s->precision, k, 0, s->stream);
+        if (timed) HIPCHK(hipEventRecord(s->ev0, s->stream));
+        launch_density(s->P, s->B, s->precision, s->lpa, k, s->stream, k == 0);
+        if (timed) HIPCHK(hipEventRecord(s->ev1, s->stream));
+        Params pt = s->P;
+        pt.ktime = timed ? 1 : 0;
+        launch_force(pt, s->B, s->precision, s->lpa, k, (s->P.fold && m == 1 && k == nd - 1) ? 2 : 0, s->stream);
+        if (timed) HIPCHK(hipEventRecord(s->ev2, s->stream));
+      }
+      done = nd;
+      if (K > nd) launch_set_base(s->B, step + nd, s->stream);
     }
     check_launch();
     if (K > done) HIPCHK(hipGraphLaunch(get_graph(s, K - done, build && !timing, m).exec, s->stream));
-    st = chunk_stats(s, timing ? s->ntot * s->lpa / kBlock : 0);
+    st = chunk_stats(s, (timing && nd == 2) ? s->ntot * s->lpa / kBlock : 0);
     s->list_builds += s->h_ctl->nbuild - s->nbuild_seen;
     s->nbuild_seen = s->h_ctl->nbuild;
     const int err = s->h_ctl->err;
-    if (err & (E_DRIFT | E_OVERFLOW | E_SKIN | E_WIDE)) {
+    if (err & (E_DRIFT | E_OVERFLOW | E_SKIN | E_WIDE | E_PRUNE)) {
       // a bound the lists rely on did not hold: re-run the chunk from its start
       snapshot(s, true);
       s->stats_valid = false;
+      if (err & E_PRUNE) prune_room *= 1.5;  // for the rest of the burst
       if (err & E_WIDE) s->P.list16 = 0;
       if (err & (E_OVERFLOW | E_WIDE)) alloc_list(s, (err & E_OVERFLOW) ? s->cap * 3 / 2 : s->cap);
       clear_err(s);
@@ -860,9 +906,11 @@ static void run_burst(ptamd_system *s, int64_t n_steps, ptamd_averages *out, con
       s->list_builds++;
       s->need_build = false;
     }
-    if (timing) {
+    if (timing && nd == 2) {
       float ms = 0.f;
       HIPCHK(hipEventElapsedTime(&ms, s->ev0, s->ev1));
+      s->t_den_ms += ms;
+      HIPCHK(hipEventElapsedTime(&ms, s->ev1, s->ev2));
       s->t_ev_ms += ms;
       // the stamps were folded into the control block with the statistics
       s->t_sum_ms += (double)(s->h_ctl->kt_last - s->h_ctl->kt_first) / s->wall_khz;
@@ -1154,13 +1202,14 @@ static void get_neighbors(ptamd_system *s, int64_t *offsets, int32_t *idx, int64
   s->need_sort = true;
   initial_forces(s);  // sorts, rebuilds the lists at the current positions
   const int64_t N = s->ntot;
-  std::vector<int32_t> o(N), cnt(N);
+  std::vector<int32_t> o(N), cnt(N), base(N);
   const bool l16 = s->P.list16 != 0;
   std::vector<int32_t> nb((size_t)N * s->cap / (l16 ? 2 : 1));
   d2h(s, o.data(), s->B.orig, 4 * N);
   d2h(s, cnt.data(), s->B.ncount, 4 * N);
   d2h(s, nb.data(), s->B.nbr, nb.size() * 4);
-  const int16_t *nb16 = reinterpret_cast<const int16_t *>(nb.data());
+  if (l16) d2h(s, base.data(), s->B.nbase, 4 * N);
+  const uint16_t *nb16 = reinterpret_cast<const uint16_t *>(nb.data());
   std::vector<std::vector<int32_t>> rows(s->nreal);
   for (int64_t i = 0; i < N; ++i) {
     if (o[i] < 0) continue;
@@ -1170,7 +1219,7 @@ static void get_neighbors(ptamd_system *s, int64_t *offsets, int32_t *idx, int64
       int32_t j;
       if (l16) {
         const int w = nb16[nbr16_index(i, e, s->lpa, s->P.nbr_stride)];
-        j = w == kOffSentinel ? (int32_t)N : (int32_t)(i + w);
+        j = w == kOffSentinel ? (int32_t)N : base[i] + w;
       } else {
         j = nb[nbr_index(i, e, s->lpa, s->P.nbr_stride)];
       }
@@ -1216,22 +1265,28 @@ static void get_cells(ptamd_system *s, int32_t *cxyz, double *origin, double *in
   }
 }
 
-static void count_pairs(ptamd_system *s, int64_t *pairs, int64_t *entries) {
-  if (s->need_sort) initial_forces(s);
+static void count_pairs(ptamd_system *s, int64_t *pairs, int64_t *entries, int64_t *pruned) {
+  if (s->need_sort) {
+    initial_forces(s);  // new lists: no pruned ones yet
+    s->P.inner = 0;
+    s->rin = 0.0;
+  }
   const size_t nst = (size_t)s->n_rep * kSlots * kStat;
   launch_fill_i64(s->B.stat, (int64_t)nst, 0ull, s->stream);
   launch_count_pairs(s->P, s->B, s->precision, s->stream);
   check_launch();
   d2h(s, s->h_stat, s->B.stat, nst * 8);
   s->stats_valid = false;
-  unsigned long long p = 0, e = 0;
+  unsigned long long p = 0, e = 0, q = 0;
   for (int r = 0; r < s->n_rep; ++r)
     for (int sl = 0; sl < kSlots; ++sl) {
       p += s->h_stat[((size_t)r * kSlots + sl) * kStat];
       e += s->h_stat[((size_t)r * kSlots + sl) * kStat + 1];
+      q += s->h_stat[((size_t)r * kSlots + sl) * kStat + 2];
     }
   *pairs = (int64_t)(p / 2);
   *entries = (int64_t)e;
+  if (pruned) *pruned = (int64_t)q;
 }
 
 // ---------------------------------------------------------------------------
@@ -1297,7 +1352,9 @@ static void autotune(ptamd_system *s, int64_t probe_steps, int use_cache, int *o
     d2d(s, save_g, s->B.group, N);
     sync(s);
     const int lpas[4] = {2, 4, 8, 16};
-    const double skins[4] = {0.6, 0.8, 1.0, 1.5};
+    // (with pruned lists the skin sets only how often the full lists are
+    // built and how many entries each pruning pass reads)
+    const double skins[4] = {0.8, 1.0, 1.5, 2.0};
     std::vector<ptamd_averages> tmp(s->n_rep);
     // two rounds over all candidates, each candidate timed by its faster
     // round: a single probe is noisy enough to flip close choices
@@ -1379,6 +1436,7 @@ static void destroy(ptamd_system *s) {
   if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
   if (s->ev0) (void)hipEventDestroy(s->ev0);
   if (s->ev1) (void)hipEventDestroy(s->ev1);
+  if (s->ev2) (void)hipEventDestroy(s->ev2);
   delete s;
 }
 
@@ -1676,17 +1734,20 @@ ptamd_status ptamd_set_stream(ptamd_system *sys, void *hip_stream) {
   });
 }
 
-ptamd_status ptamd_kernel_timing(ptamd_system *sys, double *avg_ms, double *avg_event_ms, int64_t *count,
-                                 int32_t reset) {
+ptamd_status ptamd_kernel_timing(ptamd_system *sys, double *avg_ms, double *avg_event_ms, double *density_event_ms,
+                                 int64_t *count, int32_t reset) {
   return guard([&] {
     if (!sys) fail(PTAMD_EINVAL, "NULL system");
     sys->timing = true;
-    if (avg_ms) *avg_ms = sys->t_count ? sys->t_sum_ms / (double)sys->t_count : 0.0;
-    if (avg_event_ms) *avg_event_ms = sys->t_count ? sys->t_ev_ms / (double)sys->t_count : 0.0;
+    const double n = (double)sys->t_count;
+    if (avg_ms) *avg_ms = sys->t_count ? sys->t_sum_ms / n : 0.0;
+    if (avg_event_ms) *avg_event_ms = sys->t_count ? sys->t_ev_ms / n : 0.0;
+    if (density_event_ms) *density_event_ms = sys->t_count ? sys->t_den_ms / n : 0.0;
     if (count) *count = sys->t_count;
     if (reset) {
       sys->t_sum_ms = 0.0;
       sys->t_ev_ms = 0.0;
+      sys->t_den_ms = 0.0;
       sys->t_count = 0;
     }
   });
@@ -1705,11 +1766,13 @@ ptamd_status ptamd_autotune(ptamd_system *sys, int64_t probe_steps, int32_t use_
   });
 }
 
-ptamd_status ptamd_count_pairs(ptamd_system *sys, int64_t *pairs_in_rc, int64_t *list_entries) {
+ptamd_status ptamd_count_pairs(ptamd_system *sys, int64_t *pairs_in_rc, int64_t *list_entries,
+                               int64_t *pruned_entries, double *prune_radius) {
   return guard([&] {
     use_device(sys);
     if (!pairs_in_rc || !list_entries) fail(PTAMD_EINVAL, "NULL argument");
-    count_pairs(sys, pairs_in_rc, list_entries);
+    count_pairs(sys, pairs_in_rc, list_entries, pruned_entries);
+    if (prune_radius) *prune_radius = sys->rin;
   });
 }
 

@@ -222,3 +222,4 @@ def test_cube50_every_atom_mixed():
     print(f"\nN={n} mixed, lists of {info['list_index_bits']}-bit entries: forces max {fe:.2e} rms {fr:.2e}, "
           f"U/atom {ue:.2e}")
     assert fe <= 2e-4 and ue <= 1e-5
+    assert info["list_index_bits"] == 16

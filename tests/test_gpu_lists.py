@@ -1,15 +1,15 @@
 """Forms of the Verlet lists and of the step, through the C ABI.
 
-Lists start in the 16-bit form (each entry the offset j - i of the
-neighbour in the sorted order); every other GPU test of a small system runs
-on it.  A system whose offsets outgrow 16 bits switches to 32-bit indices
-at the list build that meets one.  Here a film 20 A thick, whose sorted
-order puts ~27,000 atoms in each of its three layers of bins (an atom of
-the first layer has neighbours up to ~58,000 places on), forces that switch; its forces and
-neighbour sets are checked against the oracle on sampled atoms (forces
-relative to max(|F|, F_rms): FP64 1e-9; mixed 2e-4, the parity tests' bar,
-where coordinates up to 260 A put the FP32 rounding of positions at
-1.5e-5 A; measured 8e-5).
+Lists start in the 16-bit form (each entry the offset of the neighbour in
+the sorted order from the smallest index in the atom's list); every other
+GPU test of a small system runs on it, and so does the 500,000-atom cube.
+A system whose offsets outgrow 16 bits switches to 32-bit indices at the
+list build that meets one.  Here a film 20 A thick and 389 A wide, whose
+sorted order puts ~60,000 atoms in each of its layers of bins (the
+neighbours of an atom of the middle layer span about two layers, ~120,000
+places), forces that switch; its forces and neighbour sets are checked
+against the oracle on sampled atoms (forces relative to max(|F|, F_rms):
+FP64 1e-9; mixed 2e-4, the parity tests' bar).
 """
 import numpy as np
 import pytest
@@ -45,7 +45,7 @@ def test_fold_threshold():
 
 @pytest.fixture(scope="module")
 def film():
-    return synth.fcc_slab(64, 64, 5, 0.05, 61)  # 81,920 atoms, 20 A thick
+    return synth.fcc_slab(96, 96, 5, 0.05, 61)  # 184,320 atoms, 20 A thick
 
 
 @pytest.mark.parametrize("precision", [0, 1])
