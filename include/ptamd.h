@@ -202,6 +202,16 @@ ptamd_status ptamd_eam_table_eval(const ptamd_eam_table *table, int32_t which, i
 ptamd_status ptamd_apply_strain_increment(ptamd_system *sys, double d_eps);
 /* Per-replica increments: d_eps has n_replicas entries. */
 ptamd_status ptamd_apply_strain_increments(ptamd_system *sys, const double *d_eps);
+/* For callers that cannot allocate memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same as
+ * ptamd_apply_strain_increments, with the same results, but it allocates
+ * nothing.  The per-replica scale factors go to a static device array of
+ * the library, one per GPU, set up when the first system is created on it;
+ * at most 4096 replicas per call (PTAMD_EINVAL beyond, with a message).
+ * Every call on one GPU shares that array and overwrites it, so calls that
+ * overlap on one GPU (systems driven from different threads or streams)
+ * race; calls in sequence do not.  d_eps: caller-owned, n_replicas entries. */
+ptamd_status ptamd_apply_strain_increments_noalloc(ptamd_system *sys, const double *d_eps);
 /* One averaging burst of n_steps >= 1 steps (Sec. 2.3 velocity Verlet,
  * Eqs. (vv_algo_pos_pred_half), (vv_algo_pos_pred), (vv_algo_vel_pred), with
  * fixed regions and the optional Berendsen thermostat).  Forces are

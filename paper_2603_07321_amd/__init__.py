@@ -150,6 +150,7 @@ SIGNATURES = {
     "ptamd_destroy_system": [_SYS],
     "ptamd_apply_strain_increment": [_SYS, C.c_double],
     "ptamd_apply_strain_increments": [_SYS, _P],
+    "ptamd_apply_strain_increments_noalloc": [_SYS, _P],
     "ptamd_run_fast_md": [_SYS, C.c_int64, C.POINTER(Averages)],
     "ptamd_run_until_converged": [_SYS, C.POINTER(ConvParams), C.POINTER(Averages), _P],
     "ptamd_set_eam_table": [_SYS, C.POINTER(EAMTable)],
@@ -272,6 +273,15 @@ def apply_strain_increment(sys: int, d_eps: float) -> None:
 def apply_strain_increments(sys: int, d_eps) -> None:
     d = np.ascontiguousarray(d_eps, np.float64)
     _check(_lib.ptamd_apply_strain_increments(sys, _ptr(d)))
+
+
+def apply_strain_increments_noalloc(sys: int, d_eps) -> None:
+    """ptamd_apply_strain_increments_noalloc: the same increments without any
+    allocation inside the library (one entry per replica)."""
+    d = np.ascontiguousarray(d_eps, np.float64)
+    if d.ndim != 1 or len(d) != get_info(sys)["n_replicas"]:
+        raise ValueError("need one strain increment per replica")
+    _check(_lib.ptamd_apply_strain_increments_noalloc(sys, _ptr(d)))
 
 
 def get_info(sys: int) -> dict:
@@ -536,6 +546,9 @@ class System:
 
     def apply_strain_increments(self, d_eps):
         apply_strain_increments(self.h, d_eps)
+
+    def apply_strain_increments_noalloc(self, d_eps):
+        apply_strain_increments_noalloc(self.h, d_eps)
 
     def run_fast_md(self, n_steps: int):
         return run_fast_md(self.h, n_steps)

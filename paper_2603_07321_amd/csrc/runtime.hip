@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -231,10 +232,11 @@ static void free_buffers(Buffers &b) {
 }
 
 static void upload_reps(ptamd_system *s) {
-  std::vector<RepInfo> ri(s->n_rep);
+  // the staging buffer is pinned and only rewritten after a later sync
+  sync(s);
   for (int r = 0; r < s->n_rep; ++r) {
     const RepHost &h = s->reps[r];
-    RepInfo &d = ri[r];
+    RepInfo &d = s->h_rep[r];
     std::memset(&d, 0, sizeof(d));
     d.abeg = h.abeg; d.aend = h.aend; d.nreal = h.nreal; d.nmob = h.nmob;
     d.T0 = h.T0;
@@ -251,9 +253,6 @@ static void upload_reps(ptamd_system *s) {
     d.cell_off = h.cell_off;
     d.ncells = h.ncells;
   }
-  // the staging buffer is pinned and only rewritten after a later sync
-  sync(s);
-  std::memcpy(s->h_rep, ri.data(), sizeof(RepInfo) * s->n_rep);
   HIPCHK(hipMemcpyAsync(s->B.rep, s->h_rep, sizeof(RepInfo) * s->n_rep, hipMemcpyHostToDevice, s->stream));
 }
 
@@ -310,6 +309,32 @@ static void ensure_series(ptamd_system *s, int64_t rows) {
 }
 
 // ---------------------------------------------------------------------------
+// static scratch of the allocation-free entry point
+// ---------------------------------------------------------------------------
+// The per-replica scale factors that k_strain reads sit in a static device
+// array here instead of a buffer allocated per call.  In host code the
+// array's name is no device address: its address on each device is taken
+// once (hipGetSymbolAddress, with that device current) when the first system
+// is created there, and only that address is used.  Every call on a device
+// shares its array, so calls that overlap on one device (systems on
+// different streams) race.
+constexpr int kScratchReplicas = 4096;  // 32 KiB of factors per device
+static __device__ __align__(256) double scratch[kScratchReplicas];
+constexpr int kMaxDevices = 64;
+static double *g_scratch[kMaxDevices];
+static std::mutex g_scratch_mu;
+
+static void scratch_setup(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) fail(PTAMD_ENODEV, "device index beyond the library's device table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch[dev]) return;
+  void *ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) fail(PTAMD_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  g_scratch[dev] = static_cast<double *>(ptr);
+}
+
+// ---------------------------------------------------------------------------
 // creation from per-replica host states
 // ---------------------------------------------------------------------------
 static ptamd_system *create_from_hosts(const std::vector<HostState> &hs, const std::vector<double> &T0,
@@ -317,6 +342,7 @@ static ptamd_system *create_from_hosts(const std::vector<HostState> &hs, const s
   auto *s = new ptamd_system();
   try {
     require_device(&s->device);
+    scratch_setup(s->device);
     s->n_rep = (int)hs.size();
     s->precision = md.precision;
     s->sc = sc;
@@ -982,6 +1008,40 @@ static void apply_strains(ptamd_system *s, const double *d_eps) {
 }
 
 // ---------------------------------------------------------------------------
+// allocation-free strain increments
+// ---------------------------------------------------------------------------
+// As apply_strains, with the factors staged through the system's pinned
+// statistics buffer into the device's scratch array: no device or host
+// memory is allocated.
+static void apply_strains_noalloc(ptamd_system *s, const double *d_eps) {
+  if (s->n_rep > kScratchReplicas)
+    fail(PTAMD_EINVAL, "the allocation-free strain increment takes at most " + std::to_string(kScratchReplicas) +
+                           " replicas (this system has " + std::to_string(s->n_rep) + ")");
+  double *fac = (s->device >= 0 && s->device < kMaxDevices) ? g_scratch[s->device] : nullptr;
+  if (!fac) fail(PTAMD_EDEVICE, "the scratch array of this device was not set up");
+  for (int r = 0; r < s->n_rep; ++r) {
+    if (!std::isfinite(d_eps[r]) || !(std::fabs(d_eps[r]) < 0.05)) fail(PTAMD_EINVAL, "need |d_eps| < 0.05");
+    const double e_new = s->reps[r].strain + d_eps[r];
+    if (!(1.0 + e_new > 0.0)) fail(PTAMD_EINVAL, "strain would invert the sample");
+  }
+  sync(s);  // the pinned staging buffer is free
+  double *stage = reinterpret_cast<double *>(s->h_stat);  // n_rep * kSlots * kStat entries
+  for (int r = 0; r < s->n_rep; ++r) {
+    const double e_old = s->reps[r].strain, e_new = e_old + d_eps[r];
+    stage[r] = (1.0 + e_new) / (1.0 + e_old);
+    s->reps[r].strain = e_new;
+  }
+  s->stats_valid = false;
+  HIPCHK(hipMemcpyAsync(fac, stage, 8 * (size_t)s->n_rep, hipMemcpyHostToDevice, s->stream));
+  launch_strain(s->P, s->B, fac, s->stream);
+  launch_pos4(s->P, s->B, s->precision, s->stream);
+  check_launch();
+  upload_reps(s);  // (waits for the copy above before the staging buffers are reused)
+  sync(s);
+  s->need_sort = true;
+}
+
+// ---------------------------------------------------------------------------
 // observables beyond the burst averages
 // ---------------------------------------------------------------------------
 // Per-atom position sums over the samples of each burst (Eq. (mean_pos)),
@@ -1575,6 +1635,14 @@ ptamd_status ptamd_apply_strain_increments(ptamd_system *sys, const double *d_ep
     use_device(sys);
     if (!d_eps) fail(PTAMD_EINVAL, "d_eps is NULL");
     apply_strains(sys, d_eps);
+  });
+}
+
+ptamd_status ptamd_apply_strain_increments_noalloc(ptamd_system *sys, const double *d_eps) {
+  return guard([&] {
+    use_device(sys);
+    if (!d_eps) fail(PTAMD_EINVAL, "d_eps is NULL");
+    apply_strains_noalloc(sys, d_eps);
   });
 }
 
