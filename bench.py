@@ -269,6 +269,7 @@ def main() -> int:
             "lanes_per_atom": lanes,
             "skin_A": skin,
             "list_index_bits": r["info1"]["list_index_bits"],
+            "list_widened": {"step": r["info1"]["wide_step"], "by": r["info1"]["wide_where"]},
             "full_lists": bool(fl),
             "tuning": r["tune"],
         },

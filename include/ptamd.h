@@ -129,10 +129,13 @@ typedef struct {
     int64_t steps;           /* MD steps since creation */
     double skin;
     double bin_margin;
-    int32_t list_index_bits; /* 16: list entries are 16-bit offsets j - i; 32: indices (a system
-                                switches for good when a list build meets an offset beyond 16 bits) */
+    int32_t list_index_bits; /* 16: list entries are 16-bit steps between a lane's consecutive
+                                neighbour indices; 32: indices (a system switches for good when a
+                                list build or pruning pass meets a step beyond 16 bits) */
     int32_t folded;          /* 1: each step's kick-drift runs inside its density pass (mixed form,
                                 up to 131,072 padded atoms) */
+    int64_t wide_step;       /* MD step since creation at which the lists switched to 32 bits (-1: never) */
+    int32_t wide_where;      /* what met the wide step: 1 a list build, 2 a pruning pass, 0 none */
 } ptamd_info;
 
 /* ---- creation ---- */

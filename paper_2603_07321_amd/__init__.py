@@ -130,7 +130,8 @@ class Info(C.Structure):
     _fields_ = [("n_atoms", C.c_int64), ("n_replicas", C.c_int32), ("precision", C.c_int32),
                 ("lanes_per_atom", C.c_int32), ("list_capacity", C.c_int32), ("list_builds", C.c_int64),
                 ("sorts", C.c_int64), ("rollbacks", C.c_int64), ("steps", C.c_int64), ("skin", C.c_double),
-                ("bin_margin", C.c_double), ("list_index_bits", C.c_int32), ("folded", C.c_int32)]
+                ("bin_margin", C.c_double), ("list_index_bits", C.c_int32), ("folded", C.c_int32),
+                ("wide_step", C.c_int64), ("wide_where", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

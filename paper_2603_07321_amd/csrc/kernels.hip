@@ -95,6 +95,8 @@ template <int LPA> __device__ __forceinline__ int pass_slots(int cnt) {
   return (cnt + kPass * LPA - 1) / (kPass * LPA) * kPass;
 }
 
+__device__ __forceinline__ void set_err(const Buffers &b, int bits) { atomicOr(&b.ctl->err, bits); }
+
 // Gather of one position entry: a uniform base plus a 32-bit byte offset
 // (the global-load form with a scalar base), one shift per gather instead of
 // 64-bit address arithmetic.  Indices stay below 2^27 (checked at creation).
@@ -126,43 +128,44 @@ __device__ __forceinline__ void gather8(const V4 *p4, int4 la, int4 lb, V4 (&pj)
 // them, and their latency (the list streams from HBM or the Infinity Cache)
 // hides behind this pass's arithmetic.  The scheduling barriers keep that
 // issue order.  (Gathering the next pass's positions ahead as well, into a
-// second buffer, measured slower on the 62,500-atom cube.)  body(pj, raw)
-// evaluates eight gathered entries; raw holds the entries as stored (the
-// pruning density pass copies them into the pruned list).
-// Index of a 16-bit list entry w of an atom whose offsets count from base
-// (sent: the sentinel's index).
-__device__ __forceinline__ int off_index(unsigned w, int base, int sent) {
-  return w == (unsigned)kOffSentinel ? sent : base + (int)w;
-}
-
-// L16: the 16-bit form, one 16-byte group (eight offsets) per pass.
+// second buffer, measured slower on the 62,500-atom cube.)  body(pj, jv)
+// evaluates eight gathered entries; jv holds their indices (the pruning
+// density pass writes them into the pruned list).
+// L16: the 16-bit form, one 16-byte group (eight entries) per pass; each
+// entry is the step from the lane's previous entry (from the atom's base
+// for its first), kOffSentinel the sentinel (only ever after the last real
+// entry of a lane, so the running index may run on past it).
 template <bool L16, class V4, class Body>
 __device__ __forceinline__ void pair_passes(const V4 *p4, const int4 *nb4, int64_t stride, int npl, int base,
                                             int sent, Body &&body) {
   V4 pj[8];
-  int raw[8];
+  int jv[8];
   if (L16) {
+    int jp = base;
     int4 la = nb4[0];
     for (int s = 0; s < npl; s += kPass) {
       const unsigned w[4] = {(unsigned)la.x, (unsigned)la.y, (unsigned)la.z, (unsigned)la.w};
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        raw[2 * u] = (int)(w[u] & 0xffffu);
-        raw[2 * u + 1] = (int)(w[u] >> 16);
-        pj[2 * u] = gather<V4>(p4, off_index(w[u] & 0xffffu, base, sent));
-        pj[2 * u + 1] = gather<V4>(p4, off_index(w[u] >> 16, base, sent));
+        const unsigned lo = w[u] & 0xffffu, hi = w[u] >> 16;
+        jp += (int)lo;
+        jv[2 * u] = lo == (unsigned)kOffSentinel ? sent : jp;
+        jp += (int)hi;
+        jv[2 * u + 1] = hi == (unsigned)kOffSentinel ? sent : jp;
+        pj[2 * u] = gather<V4>(p4, jv[2 * u]);
+        pj[2 * u + 1] = gather<V4>(p4, jv[2 * u + 1]);
       }
       __builtin_amdgcn_sched_barrier(0);
       if (s + kPass < npl) la = nb4[(size_t)((s + kPass) / kGroup16) * stride];
       __builtin_amdgcn_sched_barrier(0);
-      body(pj, raw);
+      body(pj, jv);
     }
     return;
   }
   int4 la = nb4[0], lb = nb4[stride];
   for (int s = 0; s < npl; s += kPass) {
-    raw[0] = la.x; raw[1] = la.y; raw[2] = la.z; raw[3] = la.w;
-    raw[4] = lb.x; raw[5] = lb.y; raw[6] = lb.z; raw[7] = lb.w;
+    jv[0] = la.x; jv[1] = la.y; jv[2] = la.z; jv[3] = la.w;
+    jv[4] = lb.x; jv[5] = lb.y; jv[6] = lb.z; jv[7] = lb.w;
     gather8(p4, la, lb, pj);
     __builtin_amdgcn_sched_barrier(0);
     if (s + kPass < npl) {
@@ -170,39 +173,93 @@ __device__ __forceinline__ void pair_passes(const V4 *p4, const int4 *nb4, int64
       lb = nb4[(size_t)((s + kPass) / kGroup + 1) * stride];
     }
     __builtin_amdgcn_sched_barrier(0);
-    body(pj, raw);
+    body(pj, jv);
   }
 }
 
 // Pruned lists.  The pruning density pass keeps, of every pass of the full
-// list, the entries within rin of the atom and writes them, in the order
-// they were met (pass, then slot, then lane), round-robin over the atom's
+// list, the entries within rin of the atom, in the order they were met
+// (pass, then slot, then lane), and deals them round-robin over the atom's
 // lanes: kept entry e goes to lane e % LPA, slot e / LPA, so the lanes of an
 // atom hold equal shares and the pruned list has the full list's layout.
-// cnt (equal in the atom's lanes) counts the kept entries so far.
+// The kept indices of each pass go to a ring in LDS (16 LPA words per atom:
+// what is not yet written out is less than two passes' worth); once a whole
+// pass of the pruned list (8 LPA entries) is there, each lane reads its 8
+// (stride LPA), forms its entries (16-bit form: steps from its previous
+// index, the atom's base before the first) and stores them as one or two
+// whole 16-byte groups.
 template <int LPA, bool L16>
-__device__ __forceinline__ void prune_put(const Params &p, int32_t *nbri, int64_t i, int lane, bool keep, int raw,
-                                          int &cnt) {
-  const int lb = (int)(threadIdx.x & 63) & ~(LPA - 1);
-  const unsigned long long bm = __ballot(keep);
-  const unsigned grp = (unsigned)(bm >> lb) & (unsigned)((1ull << LPA) - 1ull);
-  const int pos = cnt + __popc(grp & ((1u << lane) - 1u));
-  cnt += __popc(grp);
-  if (keep) {
-    if (L16) reinterpret_cast<uint16_t *>(nbri)[nbr16_index(i, pos, LPA, p.nbr_stride)] = (uint16_t)raw;
-    else nbri[nbr_index(i, pos, LPA, p.nbr_stride)] = raw;
-  }
-}
+struct PruneWriter {
+  static constexpr int kWin = kPass * LPA;  // entries of one pass of all the atom's lanes
+  static constexpr int kRing = 2 * kWin;    // a power of two
+  int *ring;  // this atom's kRing words of LDS
+  int cnt;    // entries kept so far (equal in the atom's lanes)
+  int done;   // entries written out (a multiple of kWin)
+  int last;   // 16-bit form: this lane's last index written
 
-// Sentinel entries after the cnt kept ones, up to whole passes of all lanes.
-template <int LPA, bool L16>
-__device__ __forceinline__ void prune_pad(const Params &p, int32_t *nbri, int64_t i, int lane, int cnt) {
-  const int padded = pass_slots<LPA>(cnt) * LPA;
-  for (int e = cnt + lane; e < padded; e += LPA) {
-    if (L16) reinterpret_cast<uint16_t *>(nbri)[nbr16_index(i, e, LPA, p.nbr_stride)] = (uint16_t)kOffSentinel;
-    else nbri[nbr_index(i, e, LPA, p.nbr_stride)] = (int)p.ntot;
+  __device__ __forceinline__ void init(int *lds, int base) {
+    ring = lds + (int)(threadIdx.x / LPA) * kRing;
+    cnt = done = 0;
+    last = base;
   }
-}
+
+  // one pass of the full list: keep[u], jv[u] of this lane's slot u
+  __device__ __forceinline__ void pass(const Params &p, const Buffers &b, int64_t i, int lane, const bool (&keep)[8],
+                                       const int (&jv)[8]) {
+    const int lb = (int)(threadIdx.x & 63) & ~(LPA - 1);
+    const unsigned below = (1u << lane) - 1u;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const unsigned m = (unsigned)(__ballot(keep[u]) >> lb) & (unsigned)((1ull << LPA) - 1ull);
+      if (keep[u]) ring[(cnt + __popc(m & below)) & (kRing - 1)] = jv[u];
+      cnt += __popc(m);
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    if (cnt - done >= kWin) flush(p, b, i, lane);
+  }
+
+  // writes entries done .. done + kWin - 1 (sentinels from cnt on)
+  __device__ __forceinline__ void flush(const Params &p, const Buffers &b, int64_t i, int lane) {
+    const int row = done / kWin;  // pass of the pruned list
+    int v[8];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int e = done + s * LPA + lane;
+      if (e < cnt) {
+        const int j = ring[e & (kRing - 1)];
+        if (L16) {
+          const int d = j - last;
+          last = j;
+          const bool fits = d >= 0 && d < kOffSentinel;
+          if (!fits) set_err(b, E_WIDE_PRUNED);
+          v[s] = fits ? d : kOffSentinel;
+        } else {
+          v[s] = j;
+        }
+      } else {
+        v[s] = L16 ? kOffSentinel : (int)p.ntot;
+      }
+    }
+    int4 *out = reinterpret_cast<int4 *>(b.nbri);
+    if (L16) {
+      out[(size_t)row * p.nbr_stride + (size_t)i * LPA + lane] =
+          make_int4(v[0] | (v[1] << 16), v[2] | (v[3] << 16), v[4] | (v[5] << 16), v[6] | (v[7] << 16));
+    } else {
+      out[(size_t)(2 * row) * p.nbr_stride + (size_t)i * LPA + lane] = make_int4(v[0], v[1], v[2], v[3]);
+      out[(size_t)(2 * row + 1) * p.nbr_stride + (size_t)i * LPA + lane] = make_int4(v[4], v[5], v[6], v[7]);
+    }
+    done += kWin;
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  }
+
+  // the last, partial pass
+  __device__ __forceinline__ void finish(const Params &p, const Buffers &b, int64_t i, int lane) {
+    if (cnt > done) flush(p, b, i, lane);
+    if (lane == 0) b.ncounti[i] = cnt;
+  }
+};
 
 // Tabulated potential (NM = 2): interval and offset of r in the r tables.
 // Pairs have r < rc <= (nr - 1) dr; the clamp keeps rounding at the last
@@ -285,7 +342,6 @@ __device__ __forceinline__ unsigned long long *slot_row(const Buffers &b, int n_
   return b.slots + (((size_t)par * n_rep + r) * kSlots + slot) * kNQ;
 }
 
-__device__ __forceinline__ void set_err(const Buffers &b, int bits) { atomicOr(&b.ctl->err, bits); }
 
 // Atoms the integrator moves: mobile atoms (group 0) along x, y, z; during
 // thermal relaxation the top region (group 2) along z only.  Every other
@@ -865,10 +921,15 @@ __device__ void build_one(const Params &p, const Buffers &b, int64_t i, int lane
   const size_t group_stride = (size_t)p.nbr_stride * kGroup;
   int cnt = 0;
   bool wide = false;  // an offset beyond 16 bits met (reported once per atom below)
-  // 16-bit form: offsets count from the first index kept, which is the
-  // smallest (rows are met in increasing sorted order, and each row's atoms
-  // in order)
+  // 16-bit form: each entry is the step from the entry LPA places before it
+  // (the same lane's previous one), the first LPA from the atom's base, the
+  // first index kept, which is the smallest (rows are met in increasing
+  // sorted order, and each row's atoms in order).  ring (LDS, 64 words per
+  // atom) holds the indices of the last kept entries by position: a ballot
+  // keeps at most KB, and an entry looks back LPA <= KB places.
   int base = -1;
+  __shared__ int ring[kBlock / KB][64];
+  int *rg = ring[threadIdx.x / KB];
   for (int q = 0; q < 25; ++q) {
     const int src = gbase + (q % KB);
     int rq = rs[0], eq = re[0];
@@ -902,10 +963,21 @@ __device__ void build_one(const Params &p, const Buffers &b, int64_t i, int lane
         // (uniform over the atom's lanes; the source lane is one of them)
         if (L16 && base < 0 && m != 0) base = __shfl(j, gbase + __ffsll((long long)m) - 1);
         const unsigned pos = (unsigned)cnt + (unsigned)__popcll(m & below);
+        int prev = base;
+        if (L16) {
+          // every kept entry's index first, then the one LPA places back
+          // (this ballot's or an earlier one's)
+          if (ok) rg[pos & 63] = j;
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+          if (ok && pos >= (unsigned)LPA) prev = rg[(pos - LPA) & 63];
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        }
         if (ok && pos < (unsigned)cap) {
           const unsigned l = pos % LPA, sl = pos / LPA;
           if (L16) {
-            const int d = j - base;
+            const int d = j - prev;
             const bool fits = d >= 0 && d < kOffSentinel;
             wide |= !fits;
             reinterpret_cast<uint16_t *>(b.nbr)[(size_t)(sl / kGroup16) * (size_t)p.nbr_stride * kGroup16 +
@@ -1017,13 +1089,18 @@ __global__ __launch_bounds__(kBlock) void k_density(Params p, Buffers b, int32_t
     const int base = L16 ? b.nbase[i] : 0;
     const int4 *nb4 = reinterpret_cast<const int4 *>(full ? b.nbr : b.nbri) + (size_t)i * LPA + lane;
     const R rin2 = PR ? (R)b.ctl->rin2 : (R)0;
-    int kept = 0;
-    pair_passes<L16>(pn, nb4, p.nbr_stride, npl, base, (int)p.ntot, [&](const V4(&pj)[8], const int(&raw)[8]) {
+    PruneWriter<LPA, L16> pw;
+    if (PR) {
+      __shared__ int ring[PR ? 2 * kPass * kBlock : 1];
+      pw.init(ring, base);
+    }
+    pair_passes<L16>(pn, nb4, p.nbr_stride, npl, base, (int)p.ntot, [&](const V4(&pj)[8], const int(&jv)[8]) {
+      bool keep[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const R dx = pj[u].x - pi.x, dy = pj[u].y - pi.y, dz = pj[u].z - pi.z;
         const R r2 = dx * dx + dy * dy + dz * dz;
-        if (PR) prune_put<LPA, L16>(p, b.nbri, i, lane, r2 < rin2, raw[u], kept);
+        keep[u] = PR && r2 < rin2;
         if (r2 < rc2) {
           const R rinv = rsqrt_r(r2);
           if (NM == 2) {
@@ -1038,11 +1115,9 @@ __global__ __launch_bounds__(kBlock) void k_density(Params p, Buffers b, int32_t
           }
         }
       }
+      if (PR) pw.pass(p, b, i, lane, keep, jv);
     });
-    if (PR) {
-      prune_pad<LPA, L16>(p, b.nbri, i, lane, kept);
-      if (lane == 0) b.ncounti[i] = kept;
-    }
+    if (PR) pw.finish(p, b, i, lane);
   }
 #pragma unroll
   for (int o = LPA / 2; o > 0; o >>= 1) {
@@ -1688,12 +1763,14 @@ __global__ __launch_bounds__(kBlock) void k_count_pairs(Params p, Buffers b) {
     const int cnt = b.ncount[i];
     ne = cnt;
     nq = p.inner ? (unsigned long long)b.ncounti[i] : 0ull;
-    for (int e = 0; e < cnt; ++e) {
-      const int j = p.list16 ? off_index(reinterpret_cast<const uint16_t *>(b.nbr)[nbr16_index(i, e, p.lpa, p.nbr_stride)],
-                                       b.nbase[i], (int)p.ntot)
-                           : b.nbr[nbr_index(i, e, p.lpa, p.nbr_stride)];
-      const double d2 = dist2_plain(b.x[j] - b.x[i], b.y[j] - b.y[i], b.z[j] - b.z[i]);
-      if (d2 < p.rc2) ++np;
+    for (int l = 0; l < p.lpa; ++l) {
+      int j = p.list16 ? b.nbase[i] : 0;  // 16-bit form: steps from the lane's previous entry
+      for (int e = l; e < cnt; e += p.lpa) {
+        if (p.list16) j += reinterpret_cast<const uint16_t *>(b.nbr)[nbr16_index(i, e, p.lpa, p.nbr_stride)];
+        else j = b.nbr[nbr_index(i, e, p.lpa, p.nbr_stride)];
+        const double d2 = dist2_plain(b.x[j] - b.x[i], b.y[j] - b.y[i], b.z[j] - b.z[i]);
+        if (d2 < p.rc2) ++np;
+      }
     }
   }
   for (int o = 32; o > 0; o >>= 1) {

@@ -36,7 +36,8 @@ enum : int {
   E_STATE = 16,    // thermostat: T <= 0 or lambda^2 < 0
   E_SKIN = 32,     // an atom moved more than half the skin since the list build (a trigger was missed)
   E_WIDE = 64,     // a list entry's offset does not fit the 16-bit list form
-  E_PRUNE = 128    // an atom moved faster than the pruned lists allow (Control::vb2)
+  E_PRUNE = 128,   // an atom moved faster than the pruned lists allow (Control::vb2)
+  E_WIDE_PRUNED = 256  // as E_WIDE, met by a pruning pass
 };
 
 // Device-resident control block (one per system).
@@ -149,7 +150,7 @@ struct Buffers {
   float *xr, *yr, *zr; // positions at the last list build
   int32_t *nbr;        // Verlet lists, [slot][atom*lpa + lane] (32-bit indices or 16-bit offsets, Params::list16)
   int32_t *ncount;     // list length per atom
-  int32_t *nbase;      // 16-bit form: the index the atom's offsets count from (its smallest listed neighbour)
+  int32_t *nbase;      // 16-bit form: the index the atom's first steps count from (its smallest listed neighbour)
   int32_t *nbri;       // pruned lists (same layout and entry form as nbr)
   int32_t *ncounti;    // pruned list length per atom
   double *eshift;      // Sutton-Chen: the pair-energy shift -n_c Vc - dVc (sum r - n_c rc) over the atom's
@@ -184,15 +185,18 @@ __host__ __device__ inline size_t nbr_index(int64_t i, int e, int lpa, int64_t s
   return ((size_t)(s / kGroup) * (size_t)stride + (size_t)i * lpa + l) * kGroup + (s % kGroup);
 }
 
-// The 16-bit form of the lists: entry e of atom i holds the unsigned offset
-// j - nbase[i], where nbase[i] is the smallest index in the atom's list
-// (sorted order keeps an atom's neighbours within a few bin layers of it:
-// with bins of edge h, those within rlist of it span less than
-// 2 rlist + h of z, about 50,000 atoms of a 500,000-atom cube), eight to a
-// group per lane, so one 16-byte load gives a lane a whole pass and the
-// pair kernels read half the list bytes.  kOffSentinel stands for the
-// sentinel index ntot.  A system whose offsets outgrow 16 bits (a build
-// meets one: E_WIDE) switches to the 32-bit form for good.
+// The 16-bit form of the lists: lane l of atom i holds its entries e = l,
+// l + lpa, ... in increasing index order, each as the unsigned step from the
+// lane's previous entry (the first from nbase[i], the smallest index in the
+// atom's list).  Sorted order keeps an atom's neighbours within a few bin
+// layers of it, and one lane's consecutive entries lie lpa entries apart in
+// the atom's sorted list, so a step exceeds a few hundred only where the list
+// moves on to the next bin row or layer: well inside 16 bits at any size
+// whose bin layers hold fewer than 65,535 atoms.  Eight entries to a group
+// per lane, so one 16-byte load gives a lane a whole pass and the pair
+// kernels read half the list bytes.  kOffSentinel (after a lane's last
+// entry) stands for the sentinel index ntot.  A system where a step outgrows
+// 16 bits (a build meets one: E_WIDE) switches to the 32-bit form for good.
 constexpr int kGroup16 = 8;
 constexpr int kOffSentinel = 0xffff;
 __host__ __device__ inline size_t nbr16_index(int64_t i, int e, int lpa, int64_t stride) {

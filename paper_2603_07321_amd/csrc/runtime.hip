@@ -123,6 +123,8 @@ struct ptamd_system {
   int64_t steps_total = 0, sorts = 0, rollbacks = 0, list_builds = 0;
   int64_t nbuild_seen = 0;  // device-side builds already counted in list_builds
   bool prune = true;        // pruned lists between pruning passes (ptamd_md_params::full_lists == 0)
+  int64_t wide_step = -1;   // step (since creation) at which the lists left the 16-bit form
+  int32_t wide_where = 0;   // 1: a full-list build met a step beyond 16 bits, 2: a pruning pass
   double rin = 0.0;         // radius of the last chunk's pruned lists (0: full lists)
   int64_t series_rows = 0;
 };
@@ -761,7 +763,11 @@ static void initial_forces(ptamd_system *s) {
   if (s->h_ctl->err & (E_OVERFLOW | E_WIDE)) {
     // grow the lists, or widen them to 32-bit indices, and try again from
     // the same positions
-    if (s->h_ctl->err & E_WIDE) s->P.list16 = 0;
+    if ((s->h_ctl->err & E_WIDE) && s->P.list16) {
+      s->P.list16 = 0;
+      s->wide_step = s->steps_total;
+      s->wide_where = 1;
+    }
     alloc_list(s, (s->h_ctl->err & E_OVERFLOW) ? s->cap * 3 / 2 : s->cap);
     clear_err(s);
     s->need_sort = true;
@@ -909,13 +915,18 @@ static void run_burst(ptamd_system *s, int64_t n_steps, ptamd_averages *out, con
     s->list_builds += s->h_ctl->nbuild - s->nbuild_seen;
     s->nbuild_seen = s->h_ctl->nbuild;
     const int err = s->h_ctl->err;
-    if (err & (E_DRIFT | E_OVERFLOW | E_SKIN | E_WIDE | E_PRUNE)) {
+    if (err & (E_DRIFT | E_OVERFLOW | E_SKIN | E_WIDE | E_WIDE_PRUNED | E_PRUNE)) {
       // a bound the lists rely on did not hold: re-run the chunk from its start
       snapshot(s, true);
       s->stats_valid = false;
       if (err & E_PRUNE) prune_room *= 1.5;  // for the rest of the burst
-      if (err & E_WIDE) s->P.list16 = 0;
-      if (err & (E_OVERFLOW | E_WIDE)) alloc_list(s, (err & E_OVERFLOW) ? s->cap * 3 / 2 : s->cap);
+      if ((err & (E_WIDE | E_WIDE_PRUNED)) && s->P.list16) {
+        s->P.list16 = 0;
+        s->wide_step = s->steps_total + step - 1;
+        s->wide_where = (err & E_WIDE) ? 1 : 2;
+      }
+      if (err & (E_OVERFLOW | E_WIDE | E_WIDE_PRUNED))
+        alloc_list(s, (err & E_OVERFLOW) ? s->cap * 3 / 2 : s->cap);
       clear_err(s);
       s->need_sort = true;
       s->rollbacks++;
@@ -1275,15 +1286,13 @@ static void get_neighbors(ptamd_system *s, int64_t *offsets, int32_t *idx, int64
     if (o[i] < 0) continue;
     auto &row = rows[o[i]];
     row.reserve(cnt[i]);
-    for (int e = 0; e < cnt[i]; ++e) {
-      int32_t j;
-      if (l16) {
-        const int w = nb16[nbr16_index(i, e, s->lpa, s->P.nbr_stride)];
-        j = w == kOffSentinel ? (int32_t)N : base[i] + w;
-      } else {
-        j = nb[nbr_index(i, e, s->lpa, s->P.nbr_stride)];
+    for (int l = 0; l < s->lpa; ++l) {
+      int32_t j = l16 ? base[i] : 0;  // 16-bit form: steps from the lane's previous entry
+      for (int e = l; e < cnt[i]; e += s->lpa) {
+        if (l16) j += nb16[nbr16_index(i, e, s->lpa, s->P.nbr_stride)];
+        else j = nb[nbr_index(i, e, s->lpa, s->P.nbr_stride)];
+        row.push_back(o[j]);
       }
-      row.push_back(o[j]);
     }
     std::sort(row.begin(), row.end());
   }
@@ -1791,6 +1800,8 @@ ptamd_status ptamd_get_info(const ptamd_system *sys, ptamd_info *info) {
     info->bin_margin = sys->margin;
     info->list_index_bits = sys->P.list16 ? 16 : 32;
     info->folded = sys->P.fold;
+    info->wide_step = sys->wide_step;
+    info->wide_where = sys->wide_where;
   });
 }
 

@@ -1,15 +1,14 @@
 """Forms of the Verlet lists and of the step, through the C ABI.
 
-Lists start in the 16-bit form (each entry the offset of the neighbour in
-the sorted order from the smallest index in the atom's list); every other
-GPU test of a small system runs on it, and so does the 500,000-atom cube.
-A system whose offsets outgrow 16 bits switches to 32-bit indices at the
-list build that meets one.  Here a film 20 A thick and 389 A wide, whose
-sorted order puts ~60,000 atoms in each of its layers of bins (the
-neighbours of an atom of the middle layer span about two layers, ~120,000
-places), forces that switch; its forces and neighbour sets are checked
-against the oracle on sampled atoms (forces relative to max(|F|, F_rms):
-FP64 1e-9; mixed 2e-4, the parity tests' bar).
+Lists start in the 16-bit form (each entry the step in the sorted order from
+the same lane's previous entry, the first from the smallest index in the
+atom's list); every other GPU test runs on it, and so does the
+500,000-atom cube.  A step beyond 16 bits arises only where a bin layer
+holds more than 65,535 atoms: a system whose build meets one switches to
+32-bit indices for good.  Here a film 20 A thick and 518 A wide, whose bin
+layers hold ~100,000 atoms each, forces that switch; its forces and
+neighbour sets are checked against the oracle on sampled atoms (forces
+relative to max(|F|, F_rms): FP64 1e-9; mixed 2e-4, the parity tests' bar).
 """
 import numpy as np
 import pytest
@@ -45,7 +44,7 @@ def test_fold_threshold():
 
 @pytest.fixture(scope="module")
 def film():
-    return synth.fcc_slab(96, 96, 5, 0.05, 61)  # 184,320 atoms, 20 A thick
+    return synth.fcc_slab(128, 128, 5, 0.05, 61)  # 327,680 atoms, 20 A thick
 
 
 @pytest.mark.parametrize("precision", [0, 1])
