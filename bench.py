@@ -56,10 +56,10 @@ def kernel_source_hash() -> str:
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def measured_traffic(workload: str, precision: int, lanes: int, skin: float):
+def measured_traffic(workload: str, precision: int, lanes: int, skin: float, prune_every: int):
     """HBM bytes per launch of each pair kernel from the committed counter
-    runs, or None where the kernel source, workload, launch shape or skin
-    differs from the profiled one."""
+    runs, or None where the kernel source, workload, launch shape, skin or
+    pruning interval differs from the profiled one."""
     try:
         with open(TRAFFIC_FILE) as fh:
             recs = json.load(fh)
@@ -67,7 +67,8 @@ def measured_traffic(workload: str, precision: int, lanes: int, skin: float):
         return None
     for t in recs.get("runs", []):
         if (t.get("kernels_hip_sha256_16") == kernel_source_hash() and t.get("workload") == workload
-                and t.get("precision") == precision and t.get("lanes_per_atom") == lanes and t.get("skin") == skin):
+                and t.get("precision") == precision and t.get("lanes_per_atom") == lanes and t.get("skin") == skin
+                and t.get("prune_every") == prune_every):
             return t.get("bytes_per_launch")
     return None
 
@@ -81,7 +82,7 @@ def stored_tuning(workload: str, precision: int):
 
 
 def run_workload(P, wl, precision, steps, warmup, burst, tune, stream, timing=True, lanes=0, skin=1.0,
-                 tune_steps=400, eps=None, full_lists=0):
+                 tune_steps=400, eps=None, full_lists=0, prune_every=0):
     """Creates the workload's system, runs warm-up load steps, picks the
     launch configuration (tune: 'stored', 'probe' or 'off') and times
     `steps` load steps."""
@@ -91,7 +92,9 @@ def run_workload(P, wl, precision, steps, warmup, burst, tune, stream, timing=Tr
         chosen = stored_tuning(wl.name, precision)
         if chosen:
             lanes, skin = chosen["lanes_per_atom"], chosen["skin"]
-    md = P.md_params(precision=precision, lanes_per_atom=lanes, skin=skin, full_lists=full_lists)
+            full_lists, prune_every = (1, 0) if chosen["prune_every"] == 0 else (0, chosen["prune_every"])
+    md = P.md_params(precision=precision, lanes_per_atom=lanes, skin=skin, full_lists=full_lists,
+                     prune_every=prune_every)
     descs = [P.lattice_desc(nc, T0, seed) for nc, T0, seed in zip(wl.n_cells, wl.T0, wl.seeds)]
     if len(descs) > 1:
         sysm = P.System.batch(descs, sc=sc, md=md)
@@ -169,6 +172,8 @@ def main() -> int:
     ap.add_argument("--tune-steps", type=int, default=400)
     ap.add_argument("--eps", type=float, default=None, help="Sutton-Chen eps in eV (default 0.0033147)")
     ap.add_argument("--full-lists", action="store_true", help="pair passes on the full Verlet lists every step")
+    ap.add_argument("--prune-every", type=int, default=0,
+                    help="with --tune off: a pruning pass every this many rebuild points (1-3; 0 = 1)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 run of the same workload")
     ap.add_argument("--fp64-steps", type=int, default=None, help="timed FP64 load steps (default: as the mixed)")
     ap.add_argument("--no-secondary", action="store_true", help="skip the 62,500-atom secondary line")
@@ -213,13 +218,15 @@ def main() -> int:
 
     fl = 1 if args.full_lists else 0
     r = run_workload(P, wl, precision, steps, args.warmup, burst, args.tune, stream, lanes=args.lanes,
-                     skin=args.skin, tune_steps=args.tune_steps, eps=args.eps, full_lists=fl)
+                     skin=args.skin, tune_steps=args.tune_steps, eps=args.eps, full_lists=fl,
+                     prune_every=args.prune_every)
     n_atoms = r["n_atoms"]
     value = n_atoms * burst * steps / r["elapsed"]
     lanes = r["info1"]["lanes_per_atom"]
     skin = r["info1"]["skin"]
     pairs = r["cnt"]["pairs_in_rc"]
-    traffic = measured_traffic(args.workload, precision, lanes, skin) or {}
+    prune_every = r["info1"]["prune_every"]
+    traffic = measured_traffic(args.workload, precision, lanes, skin, prune_every) or {}
     kt = r["kt"]
     kern = {
         "force": roofline_entry("force", kt["force_event_ms"], pairs, precision, traffic.get("force")),
@@ -268,9 +275,9 @@ def main() -> int:
             "precision": "mixed" if precision == 1 else "fp64",
             "lanes_per_atom": lanes,
             "skin_A": skin,
+            "prune_every": prune_every,
             "list_index_bits": r["info1"]["list_index_bits"],
-            "list_widened": {"step": r["info1"]["wide_step"], "by": r["info1"]["wide_where"]},
-            "full_lists": bool(fl),
+            "atoms_with_32bit_lists": r["cnt"]["wide_atoms"],
             "tuning": r["tune"],
         },
         "hbm_frac_algorithmic": BYTES_PER_ATOM_STEP[precision] * value / 1e9 / HBM_PEAK_GBS,
@@ -293,6 +300,7 @@ def main() -> int:
         v64 = n_atoms * burst * n64 / f["elapsed"]
         out["fp64"] = {"value": v64, "unit": "atom-steps/s", "load_steps": n64, "mixed_over_fp64": value / v64,
                        "lanes_per_atom": f["info1"]["lanes_per_atom"], "skin_A": f["info1"]["skin"],
+                       "prune_every": f["info1"]["prune_every"], "tuning": f["tune"],
                        "last_burst_replica0": f["last"][0] if f["last"] else None}
         f["sys"].close()
 
@@ -303,7 +311,8 @@ def main() -> int:
         out["secondary"] = {"workload": w2.name, "atoms": s2["n_atoms"],
                             "value": s2["n_atoms"] * w2.burst_steps * w2.increments / s2["elapsed"],
                             "unit": "atom-steps/s", "lanes_per_atom": s2["info1"]["lanes_per_atom"],
-                            "skin_A": s2["info1"]["skin"]}
+                            "skin_A": s2["info1"]["skin"], "prune_every": s2["info1"]["prune_every"],
+                            "tuning": s2["tune"]}
         s2["sys"].close()
 
     if not args.no_cpu_baseline:

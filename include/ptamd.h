@@ -89,12 +89,12 @@ typedef struct {
  * lanes of a wavefront that share one atom's pair sums; 0 = chosen from the
  * atom count (ptamd_autotune() measures instead), else 1, 2, 4, 8 or 16.  thermostat: 0 = NVE,
  * 1 = Berendsen with coupling time tau_fs (> 0), applied to the mobile atoms
- * at the end of each step.  full_lists: 0 (default) = every fourth step the
- * density pass prunes the Verlet lists to the pairs within rc plus what the
- * fastest atoms can close in the steps until the next pruning, and the pair
- * passes in between read those; 1 = the pair passes read the full Verlet
- * lists every step.  Results do not depend on it beyond rounding (every pair
- * term still tests r < rc). */
+ * at the end of each step.  full_lists: 0 (default) = every 4 prune_every
+ * steps (prune_every 1, 2 or 3; 0 = 1) the density pass prunes the Verlet
+ * lists to the pairs within rc plus what the fastest atoms can close in the
+ * steps until the next pruning, and the pair passes in between read those;
+ * 1 = the pair passes read the full Verlet lists every step.  Results do not
+ * depend on either beyond rounding (every pair term still tests r < rc). */
 typedef struct {
     double dt_fs;
     double tau_fs;
@@ -103,6 +103,7 @@ typedef struct {
     double skin;
     int32_t lanes_per_atom;
     int32_t full_lists;
+    int32_t prune_every;
 } ptamd_md_params;
 
 /* Burst averages over the samples r = 1..n (Eq. (R_m_t)); *_se are
@@ -130,12 +131,11 @@ typedef struct {
     double skin;
     double bin_margin;
     int32_t list_index_bits; /* 16: list entries are 16-bit steps between a lane's consecutive
-                                neighbour indices; 32: indices (a system switches for good when a
-                                list build or pruning pass meets a step beyond 16 bits) */
+                                neighbour indices (atoms whose listed indices span 16 bits or more
+                                hold 32-bit indices instead; ptamd_count_pairs counts them) */
     int32_t folded;          /* 1: each step's kick-drift runs inside its density pass (mixed form,
                                 up to 131,072 padded atoms) */
-    int64_t wide_step;       /* MD step since creation at which the lists switched to 32 bits (-1: never) */
-    int32_t wide_where;      /* what met the wide step: 1 a list build, 2 a pruning pass, 0 none */
+    int32_t prune_every;     /* pruning passes every 4 prune_every steps; 0: full lists every step */
 } ptamd_info;
 
 /* ---- creation ---- */
@@ -402,29 +402,32 @@ ptamd_status ptamd_set_stream(ptamd_system *sys, void *hip_stream);
 ptamd_status ptamd_kernel_timing(ptamd_system *sys, double *avg_ms, double *avg_event_ms, double *density_event_ms,
                                  int64_t *count, int32_t reset);
 /* Autotuner: times probe bursts of probe_steps (>= 10) steps from the
- * current state for lanes per atom in {2, 4, 8, 16} and Verlet skin in
- * {0.6, 0.8, 1.0, 1.5} A, twice each (a candidate counts with its faster
- * probe), keeps the fastest (of the candidates within 3% of it, the one
+ * current state, in two stages: lanes per atom in {2, 4, 8, 16} x Verlet
+ * skin in {1.0, 1.5, 2.0, 2.5} A, then (unless the system was created with
+ * full_lists) the pruning interval: full lists or a pruning pass every 1, 2
+ * or 3 rebuild points (4, 8 or 12 steps; prune_every 0, 1, 2, 3).  Each
+ * candidate is probed twice and counts with its faster probe; the fastest
+ * is kept (in the first stage, of the candidates within 3% of it, the one
  * with the largest skin: lists live shorter as a sample heats or
- * evaporates, which a probe from the current state does not see),
- * restores the state exactly
- * (positions, velocities, atom order), and builds the HIP graphs that
- * bursts in the chosen configuration launch (with the force-kernel timing
- * as set by ptamd_kernel_timing).  With use_cache != 0 an earlier
- * choice for the same atom count, replica count, precision and cutoff in
- * this process is reused without probing.  The choice changes summation
- * order (hence rounding), never the computed quantities.  Outputs may be
- * NULL. */
+ * evaporates, which a probe from the current state does not see).  The
+ * state is restored exactly (positions, velocities, atom order), and the
+ * HIP graphs that bursts in the chosen configuration launch are built (with
+ * the kernel timing as set by ptamd_kernel_timing).  With use_cache != 0 an
+ * earlier choice for the same atom count, replica count, precision, cutoff
+ * and list mode in this process is reused without probing.  The choice
+ * changes summation order (hence rounding), never the computed quantities.
+ * Outputs may be NULL. */
 ptamd_status ptamd_autotune(ptamd_system *sys, int64_t probe_steps, int32_t use_cache, int32_t *lanes_per_atom,
-                            double *skin, double *ms_per_step);
+                            double *skin, int32_t *prune_every, double *ms_per_step);
 /* Unique pairs within rc at the current positions (for the algorithmic
  * flop count), summed over the replicas; list_entries: entries of the full
  * Verlet lists; pruned_entries (may be NULL): entries of the pruned lists
  * as the last pruning pass left them, 0 when the last chunk ran on full
- * lists; prune_radius (may be NULL): their radius in A (0 then).  Sorts and
- * rebuilds the lists first if the state changed since the last burst. */
+ * lists; prune_radius (may be NULL): their radius in A (0 then); wide_atoms
+ * (may be NULL): atoms whose lists hold 32-bit indices.  Sorts and rebuilds
+ * the lists first if the state changed since the last burst. */
 ptamd_status ptamd_count_pairs(ptamd_system *sys, int64_t *pairs_in_rc, int64_t *list_entries,
-                               int64_t *pruned_entries, double *prune_radius);
+                               int64_t *pruned_entries, double *prune_radius, int64_t *wide_atoms);
 
 /* Achievable rates of the current device, as context for the rooflines
  * (no part of the MD path): a streaming copy of bytes (a multiple of 16,

@@ -58,7 +58,7 @@ class SCParams(C.Structure):
 class MDParams(C.Structure):
     _fields_ = [("dt_fs", C.c_double), ("tau_fs", C.c_double), ("thermostat", C.c_int32),
                 ("precision", C.c_int32), ("skin", C.c_double), ("lanes_per_atom", C.c_int32),
-                ("full_lists", C.c_int32)]
+                ("full_lists", C.c_int32), ("prune_every", C.c_int32)]
 
 
 class Averages(C.Structure):
@@ -131,7 +131,7 @@ class Info(C.Structure):
                 ("lanes_per_atom", C.c_int32), ("list_capacity", C.c_int32), ("list_builds", C.c_int64),
                 ("sorts", C.c_int64), ("rollbacks", C.c_int64), ("steps", C.c_int64), ("skin", C.c_double),
                 ("bin_margin", C.c_double), ("list_index_bits", C.c_int32), ("folded", C.c_int32),
-                ("wide_step", C.c_int64), ("wide_where", C.c_int32)]
+                ("prune_every", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -175,8 +175,9 @@ SIGNATURES = {
     "ptamd_get_info": [_SYS, C.POINTER(Info)],
     "ptamd_set_stream": [_SYS, C.c_void_p],
     "ptamd_kernel_timing": [_SYS, _D, _D, _D, C.POINTER(C.c_int64), C.c_int32],
-    "ptamd_autotune": [_SYS, C.c_int64, C.c_int32, C.POINTER(C.c_int32), _D, _D],
-    "ptamd_count_pairs": [_SYS, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64), _D],
+    "ptamd_autotune": [_SYS, C.c_int64, C.c_int32, C.POINTER(C.c_int32), _D, C.POINTER(C.c_int32), _D],
+    "ptamd_count_pairs": [_SYS, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64), _D,
+                          C.POINTER(C.c_int64)],
     "ptamd_measure_device": [C.c_int64, C.c_int32, _D, _D, _D],
     "ptamd_last_error": [],
     "ptamd_version": [],
@@ -210,8 +211,8 @@ def sc_params(eps=0.0033147, a=4.05, n=7.0, m=6.0, c=16.399, rc=8.1, shift=2) ->
 
 
 def md_params(dt_fs=1.0, tau_fs=100.0, thermostat=1, precision=0, skin=1.0, lanes_per_atom=0,
-              full_lists=0) -> MDParams:
-    return MDParams(dt_fs, tau_fs, thermostat, precision, skin, lanes_per_atom, full_lists)
+              full_lists=0, prune_every=0) -> MDParams:
+    return MDParams(dt_fs, tau_fs, thermostat, precision, skin, lanes_per_atom, full_lists, prune_every)
 
 
 def conv_params(lag=1000, n_max=50000, tol=(0.05, 0.05, 0.0, 0.05), floor=(0.0, 0.0, 0.0, 0.0)) -> ConvParams:
@@ -473,9 +474,9 @@ def kernel_timing(sys: int, reset: bool = False) -> dict:
 
 
 def autotune(sys: int, probe_steps: int = 100, use_cache: bool = True) -> dict:
-    l, sk, ms = C.c_int32(), C.c_double(), C.c_double()
-    _check(_lib.ptamd_autotune(sys, probe_steps, int(use_cache), C.byref(l), C.byref(sk), C.byref(ms)))
-    return {"lanes_per_atom": l.value, "skin": sk.value, "ms_per_step": ms.value}
+    l, sk, pe, ms = C.c_int32(), C.c_double(), C.c_int32(), C.c_double()
+    _check(_lib.ptamd_autotune(sys, probe_steps, int(use_cache), C.byref(l), C.byref(sk), C.byref(pe), C.byref(ms)))
+    return {"lanes_per_atom": l.value, "skin": sk.value, "prune_every": pe.value, "ms_per_step": ms.value}
 
 
 def measure_device(nbytes: int = 1 << 30, reps: int = 10) -> dict:
@@ -487,11 +488,13 @@ def measure_device(nbytes: int = 1 << 30, reps: int = 10) -> dict:
 
 
 def count_pairs(sys: int) -> dict:
-    """Unique pairs within rc, full-list entries, pruned-list entries and the
-    pruned lists' radius (A; 0 when the last chunk ran on full lists)."""
-    p, e, q, r = C.c_int64(), C.c_int64(), C.c_int64(), C.c_double()
-    _check(_lib.ptamd_count_pairs(sys, C.byref(p), C.byref(e), C.byref(q), C.byref(r)))
-    return {"pairs_in_rc": p.value, "list_entries": e.value, "pruned_entries": q.value, "prune_radius": r.value}
+    """Unique pairs within rc, full-list entries, pruned-list entries, the
+    pruned lists' radius (A; 0 when the last chunk ran on full lists) and the
+    atoms whose lists hold 32-bit indices."""
+    p, e, q, r, w = C.c_int64(), C.c_int64(), C.c_int64(), C.c_double(), C.c_int64()
+    _check(_lib.ptamd_count_pairs(sys, C.byref(p), C.byref(e), C.byref(q), C.byref(r), C.byref(w)))
+    return {"pairs_in_rc": p.value, "list_entries": e.value, "pruned_entries": q.value, "prune_radius": r.value,
+            "wide_atoms": w.value}
 
 
 # ---------------------------------------------------------------------------

@@ -114,13 +114,6 @@ template <class R> __device__ __forceinline__ double gorigin(const RepInfo &rp, 
   return sizeof(R) == sizeof(float) ? rp.center[d] : 0.0;
 }
 
-template <class V4>
-__device__ __forceinline__ void gather8(const V4 *p4, int4 la, int4 lb, V4 (&pj)[8]) {
-  const int jv[8] = {la.x, la.y, la.z, la.w, lb.x, lb.y, lb.z, lb.w};
-#pragma unroll
-  for (int u = 0; u < 8; ++u) pj[u] = gather<V4>(p4, jv[u]);
-}
-
 // One lane's walk over its padded list: passes of eight entries (two int4
 // groups, eight independent gathers in flight).  The list entries of the
 // next pass are loaded right after the current pass's gathers: loads return
@@ -130,20 +123,25 @@ __device__ __forceinline__ void gather8(const V4 *p4, int4 la, int4 lb, V4 (&pj)
 // issue order.  (Gathering the next pass's positions ahead as well, into a
 // second buffer, measured slower on the 62,500-atom cube.)  body(pj, jv)
 // evaluates eight gathered entries; jv holds their indices (the pruning
-// density pass writes them into the pruned list).
-// L16: the 16-bit form, one 16-byte group (eight entries) per pass; each
-// entry is the step from the lane's previous entry (from the atom's base
-// for its first), kOffSentinel the sentinel (only ever after the last real
-// entry of a lane, so the running index may run on past it).
-template <bool L16, class V4, class Body>
+// density pass writes them into the pruned list).  An atom's list is in one
+// of two forms (Buffers::nwide): 16-bit (w32 false), one 16-byte group of
+// eight entries per pass, each entry the step from the lane's previous index
+// (from the atom's base for its first), kOffSentinel the sentinel (only ever
+// after the last real entry of a lane, so the running index may run on past
+// it); or 32-bit indices, two groups of four per pass.
+template <class V4, class Body>
 __device__ __forceinline__ void pair_passes(const V4 *p4, const int4 *nb4, int64_t stride, int npl, int base,
-                                            int sent, Body &&body) {
+                                            bool w32, int sent, Body &&body) {
   V4 pj[8];
   int jv[8];
-  if (L16) {
-    int jp = base;
-    int4 la = nb4[0];
-    for (int s = 0; s < npl; s += kPass) {
+  int jp = base;
+  int4 la = nb4[0], lb = la;
+  if (w32) lb = nb4[stride];
+  for (int s = 0; s < npl; s += kPass) {
+    if (w32) {
+      jv[0] = la.x; jv[1] = la.y; jv[2] = la.z; jv[3] = la.w;
+      jv[4] = lb.x; jv[5] = lb.y; jv[6] = lb.z; jv[7] = lb.w;
+    } else {
       const unsigned w[4] = {(unsigned)la.x, (unsigned)la.y, (unsigned)la.z, (unsigned)la.w};
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
@@ -152,25 +150,19 @@ __device__ __forceinline__ void pair_passes(const V4 *p4, const int4 *nb4, int64
         jv[2 * u] = lo == (unsigned)kOffSentinel ? sent : jp;
         jp += (int)hi;
         jv[2 * u + 1] = hi == (unsigned)kOffSentinel ? sent : jp;
-        pj[2 * u] = gather<V4>(p4, jv[2 * u]);
-        pj[2 * u + 1] = gather<V4>(p4, jv[2 * u + 1]);
       }
-      __builtin_amdgcn_sched_barrier(0);
-      if (s + kPass < npl) la = nb4[(size_t)((s + kPass) / kGroup16) * stride];
-      __builtin_amdgcn_sched_barrier(0);
-      body(pj, jv);
     }
-    return;
-  }
-  int4 la = nb4[0], lb = nb4[stride];
-  for (int s = 0; s < npl; s += kPass) {
-    jv[0] = la.x; jv[1] = la.y; jv[2] = la.z; jv[3] = la.w;
-    jv[4] = lb.x; jv[5] = lb.y; jv[6] = lb.z; jv[7] = lb.w;
-    gather8(p4, la, lb, pj);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) pj[u] = gather<V4>(p4, jv[u]);
     __builtin_amdgcn_sched_barrier(0);
     if (s + kPass < npl) {
-      la = nb4[(size_t)((s + kPass) / kGroup) * stride];
-      lb = nb4[(size_t)((s + kPass) / kGroup + 1) * stride];
+      const size_t row = (size_t)((s + kPass) / kPass);  // the next pass
+      if (w32) {
+        la = nb4[(2 * row) * stride];
+        lb = nb4[(2 * row + 1) * stride];
+      } else {
+        la = nb4[row * stride];
+      }
     }
     __builtin_amdgcn_sched_barrier(0);
     body(pj, jv);
@@ -186,9 +178,10 @@ __device__ __forceinline__ void pair_passes(const V4 *p4, const int4 *nb4, int64
 // what is not yet written out is less than two passes' worth); once a whole
 // pass of the pruned list (8 LPA entries) is there, each lane reads its 8
 // (stride LPA), forms its entries (16-bit form: steps from its previous
-// index, the atom's base before the first) and stores them as one or two
-// whole 16-byte groups.
-template <int LPA, bool L16>
+// index, the atom's base before the first; they fit, as every step between
+// two indices of a 16-bit full list does) and stores them as one or two
+// whole 16-byte groups.  The pruned list takes the full list's form.
+template <int LPA>
 struct PruneWriter {
   static constexpr int kWin = kPass * LPA;  // entries of one pass of all the atom's lanes
   static constexpr int kRing = 2 * kWin;    // a power of two
@@ -196,11 +189,13 @@ struct PruneWriter {
   int cnt;    // entries kept so far (equal in the atom's lanes)
   int done;   // entries written out (a multiple of kWin)
   int last;   // 16-bit form: this lane's last index written
+  bool w32;   // the atom's lists are 32-bit indices
 
-  __device__ __forceinline__ void init(int *lds, int base) {
+  __device__ __forceinline__ void init(int *lds, int base, bool wide) {
     ring = lds + (int)(threadIdx.x / LPA) * kRing;
     cnt = done = 0;
     last = base;
+    w32 = wide;
   }
 
   // one pass of the full list: keep[u], jv[u] of this lane's slot u
@@ -214,8 +209,10 @@ struct PruneWriter {
       if (keep[u]) ring[(cnt + __popc(m & below)) & (kRing - 1)] = jv[u];
       cnt += __popc(m);
     }
+    // (a wavefront's LDS accesses take effect in program order: only the
+    // compiler is held back)
     __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    asm volatile("" ::: "memory");
     if (cnt - done >= kWin) flush(p, b, i, lane);
   }
 
@@ -228,21 +225,14 @@ struct PruneWriter {
       const int e = done + s * LPA + lane;
       if (e < cnt) {
         const int j = ring[e & (kRing - 1)];
-        if (L16) {
-          const int d = j - last;
-          last = j;
-          const bool fits = d >= 0 && d < kOffSentinel;
-          if (!fits) set_err(b, E_WIDE_PRUNED);
-          v[s] = fits ? d : kOffSentinel;
-        } else {
-          v[s] = j;
-        }
+        v[s] = w32 ? j : j - last;
+        last = j;
       } else {
-        v[s] = L16 ? kOffSentinel : (int)p.ntot;
+        v[s] = w32 ? (int)p.ntot : kOffSentinel;
       }
     }
     int4 *out = reinterpret_cast<int4 *>(b.nbri);
-    if (L16) {
+    if (!w32) {
       out[(size_t)row * p.nbr_stride + (size_t)i * LPA + lane] =
           make_int4(v[0] | (v[1] << 16), v[2] | (v[3] << 16), v[4] | (v[5] << 16), v[6] | (v[7] << 16));
     } else {
@@ -251,13 +241,17 @@ struct PruneWriter {
     }
     done += kWin;
     __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    asm volatile("" ::: "memory");
   }
 
   // the last, partial pass
-  __device__ __forceinline__ void finish(const Params &p, const Buffers &b, int64_t i, int lane) {
+  __device__ __forceinline__ void finish(const Params &p, const Buffers &b, int64_t i, int lane, int base) {
     if (cnt > done) flush(p, b, i, lane);
-    if (lane == 0) b.ncounti[i] = cnt;
+    if (lane == 0) {
+      b.ncounti[i] = cnt;
+      b.nbasei[i] = base;
+      b.nwidei[i] = w32 ? 1 : 0;
+    }
   }
 };
 
@@ -860,8 +854,13 @@ template <class R> __device__ __forceinline__ float4 to_f4(typename V4T<R>::T v)
   return make_float4((float)v.x, (float)v.y, (float)v.z, 0.f);
 }
 
-template <class R, int LPA, bool L16>
-__device__ void build_one(const Params &p, const Buffers &b, int64_t i, int lane) {
+// Atom i's list in the 16-bit form (w32 false) or as 32-bit indices (w32).
+// In the 16-bit form it returns false, having written nothing but list
+// slots, if the listed indices span 65,535 or more (the caller then builds
+// the 32-bit form): every step between two of them then fits 16 bits, and so
+// do the steps of any subset, such as the pruned list.
+template <class R, int LPA>
+__device__ bool build_one(const Params &p, const Buffers &b, int64_t i, int lane, bool w32) {
   using V4 = typename V4T<R>::T;
   const int r = b.blk_rep[i / kTile];
   const V4 *p4 = reinterpret_cast<const V4 *>(b.pos4);
@@ -920,7 +919,7 @@ __device__ void build_one(const Params &p, const Buffers &b, int64_t i, int lane
   const size_t slot_base = (size_t)self * (LPA * kGroup);
   const size_t group_stride = (size_t)p.nbr_stride * kGroup;
   int cnt = 0;
-  bool wide = false;  // an offset beyond 16 bits met (reported once per atom below)
+  int jmax = -1;  // this lane's last (largest) index kept
   // 16-bit form: each entry is the step from the entry LPA places before it
   // (the same lane's previous one), the first LPA from the atom's base, the
   // first index kept, which is the smallest (rows are met in increasing
@@ -961,28 +960,29 @@ __device__ void build_one(const Params &p, const Buffers &b, int64_t i, int lane
           ok = dist2_plain(sub_plain(b.x[j], xi), sub_plain(b.y[j], yi), sub_plain(b.z[j], zi)) < p.rlist2;
         const unsigned long long m = (__ballot(ok) >> gbase) & gmask;
         // (uniform over the atom's lanes; the source lane is one of them)
-        if (L16 && base < 0 && m != 0) base = __shfl(j, gbase + __ffsll((long long)m) - 1);
+        if (base < 0 && m != 0) base = __shfl(j, gbase + __ffsll((long long)m) - 1);
+        if (ok) jmax = j;
         const unsigned pos = (unsigned)cnt + (unsigned)__popcll(m & below);
         int prev = base;
-        if (L16) {
+        if (!w32 && m != 0) {  // (most ballots keep nothing: uniform over the atom's lanes)
           // every kept entry's index first, then the one LPA places back
-          // (this ballot's or an earlier one's)
+          // (this ballot's or an earlier one's); a wavefront's LDS accesses
+          // take effect in program order, so only the compiler is held back
           if (ok) rg[pos & 63] = j;
           __builtin_amdgcn_wave_barrier();
-          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+          asm volatile("" ::: "memory");
           if (ok && pos >= (unsigned)LPA) prev = rg[(pos - LPA) & 63];
           __builtin_amdgcn_wave_barrier();
-          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+          asm volatile("" ::: "memory");
         }
         if (ok && pos < (unsigned)cap) {
           const unsigned l = pos % LPA, sl = pos / LPA;
-          if (L16) {
-            const int d = j - prev;
-            const bool fits = d >= 0 && d < kOffSentinel;
-            wide |= !fits;
+          if (!w32) {
+            // (a step of 65,535 or more is caught by the span test below,
+            // which discards this attempt)
             reinterpret_cast<uint16_t *>(b.nbr)[(size_t)(sl / kGroup16) * (size_t)p.nbr_stride * kGroup16 +
                                                 (size_t)self * (LPA * kGroup16) + l * kGroup16 + sl % kGroup16] =
-                (uint16_t)(fits ? d : kOffSentinel);
+                (uint16_t)(j - prev);
           } else {
             b.nbr[(size_t)(sl / kGroup) * group_stride + slot_base + l * kGroup + sl % kGroup] = j;
           }
@@ -991,29 +991,37 @@ __device__ void build_one(const Params &p, const Buffers &b, int64_t i, int lane
       }
     }
   }
-  if (L16 && ((__ballot(wide) >> gbase) & gmask) != 0 && lane == 0) set_err(b, E_WIDE);
+  // the span of the listed indices, equal in the atom's KB lanes
+#pragma unroll
+  for (int o = KB / 2; o > 0; o >>= 1) jmax = max(jmax, __shfl_xor(jmax, o));
+  const bool wide = base >= 0 && jmax - base >= kOffSentinel;
+  if (!w32 && wide) return false;
   const bool over = cnt > cap;  // cnt is the same in all KB lanes (ballot counts)
   if (over) cnt = cap;
   // pad to whole passes with the sentinel (cap is a multiple of kPass * LPA)
   const int padded = (cnt + kPass * LPA - 1) / (kPass * LPA) * (kPass * LPA);
   for (int e = cnt + lane; e < padded; e += KB) {
-    if (L16) reinterpret_cast<uint16_t *>(b.nbr)[nbr16_index(i, e, LPA, p.nbr_stride)] = (uint16_t)kOffSentinel;
+    if (!w32) reinterpret_cast<uint16_t *>(b.nbr)[nbr16_index(i, e, LPA, p.nbr_stride)] = (uint16_t)kOffSentinel;
     else b.nbr[nbr_index(i, e, LPA, p.nbr_stride)] = (int)p.ntot;
   }
   if (lane == 0) {
     if (over) set_err(b, E_OVERFLOW);
     b.ncount[i] = cnt;
-    if (L16) b.nbase[i] = base < 0 ? self : base;
+    b.nbase[i] = base < 0 ? self : base;
+    // 0: 16-bit; 32-bit indices: 1 where 16 bits would fit (the next build
+    // tries them), 2 where they would not
+    b.nwide[i] = w32 ? (wide ? 2 : 1) : 0;
     b.xr[i] = (float)xi;
     b.yr[i] = (float)yi;
     b.zr[i] = (float)zi;
   }
+  return true;
 }
 
 // Grid-stride over atoms: KB lanes per atom.  cond != 0: a rebuild point
 // inside a chunk, which builds only when the step before asked for it (its
 // kick-drift, or in the mixed form the force pass before that).
-template <class R, int LPA, bool L16>
+template <class R, int LPA>
 __global__ __launch_bounds__(kBlock) void k_build(Params p, Buffers b, int32_t cond) {
   if (cond) {
     if (b.ctl->rebuild == 0) return;
@@ -1022,7 +1030,12 @@ __global__ __launch_bounds__(kBlock) void k_build(Params p, Buffers b, int32_t c
   const int lane = (int)(threadIdx.x & (KB - 1));
   const int64_t per_pass = (int64_t)gridDim.x * (kBlock / KB);
   for (int64_t i = (int64_t)blockIdx.x * (kBlock / KB) + threadIdx.x / KB; i < p.ntot; i += per_pass)
-    if (b.group[i] != kPad) build_one<R, LPA, L16>(p, b, i, lane);  // a lane group skips together
+    if (b.group[i] != kPad) {  // a lane group skips together
+      // the form the atom's last list took (2: 32-bit and wider than 16
+      // bits) is tried first; a 16-bit attempt that does not fit is redone
+      const bool w32 = b.nwide[i] == 2;
+      if (!build_one<R, LPA>(p, b, i, lane, w32)) build_one<R, LPA>(p, b, i, lane, true);
+    }
 }
 
 // In the mixed form (p.fold) the step's kick-drift is done here too.  The
@@ -1038,7 +1051,7 @@ __global__ __launch_bounds__(kBlock) void k_build(Params p, Buffers b, int32_t c
 // PR: a pruning pass (Params::inner): it walks the full list and writes the
 // pruned one (the entries within rin, Control::rin2), which the pair passes
 // of the following steps, up to the next pruning pass, read instead.
-template <class R, int LPA, int NM, bool L16, bool PR>
+template <class R, int LPA, int NM, bool PR>
 __global__ __launch_bounds__(kBlock) void k_density(Params p, Buffers b, int32_t k) {
   using V4 = typename V4T<R>::T;
   const int64_t gt = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -1086,15 +1099,16 @@ __global__ __launch_bounds__(kBlock) void k_density(Params p, Buffers b, int32_t
     // slots per lane: the list is padded with the far-away sentinel to whole
     // passes, so every slot of a pass holds a valid index
     const int npl = pass_slots<LPA>((full ? b.ncount : b.ncounti)[i]);
-    const int base = L16 ? b.nbase[i] : 0;
+    const int base = full ? b.nbase[i] : b.nbasei[i];
+    const bool w32 = (full ? b.nwide[i] : b.nwidei[i]) != 0;
     const int4 *nb4 = reinterpret_cast<const int4 *>(full ? b.nbr : b.nbri) + (size_t)i * LPA + lane;
     const R rin2 = PR ? (R)b.ctl->rin2 : (R)0;
-    PruneWriter<LPA, L16> pw;
+    PruneWriter<LPA> pw;
     if (PR) {
       __shared__ int ring[PR ? 2 * kPass * kBlock : 1];
-      pw.init(ring, base);
+      pw.init(ring, base, w32);
     }
-    pair_passes<L16>(pn, nb4, p.nbr_stride, npl, base, (int)p.ntot, [&](const V4(&pj)[8], const int(&jv)[8]) {
+    pair_passes(pn, nb4, p.nbr_stride, npl, base, w32, (int)p.ntot, [&](const V4(&pj)[8], const int(&jv)[8]) {
       bool keep[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
@@ -1117,7 +1131,7 @@ __global__ __launch_bounds__(kBlock) void k_density(Params p, Buffers b, int32_t
       }
       if (PR) pw.pass(p, b, i, lane, keep, jv);
     });
-    if (PR) pw.finish(p, b, i, lane);
+    if (PR) pw.finish(p, b, i, lane, base);
   }
 #pragma unroll
   for (int o = LPA / 2; o > 0; o >>= 1) {
@@ -1174,7 +1188,7 @@ __global__ __launch_bounds__(kBlock) void k_density(Params p, Buffers b, int32_t
 // force pass: mode 0 = step (second half kick + sums), 1 = forces only,
 // 2 = step, and the next step is a list rebuild point of the mixed form
 // ---------------------------------------------------------------------------
-template <class R, int LPA, int NM, bool L16>
+template <class R, int LPA, int NM>
 __global__ __launch_bounds__(kBlock) void k_force(Params p, Buffers b, int32_t k, int32_t mode) {
   using V4 = typename V4T<R>::T;
   const unsigned long long t_begin = p.ktime ? wall_clock64() : 0ull;
@@ -1227,9 +1241,10 @@ __global__ __launch_bounds__(kBlock) void k_force(Params p, Buffers b, int32_t k
     // slots per lane: the list is padded with the far-away sentinel to whole
     // passes, so every slot of a pass holds a valid index
     const int npl = pass_slots<LPA>((p.inner ? b.ncounti : b.ncount)[i]);
-    const int base = L16 ? b.nbase[i] : 0;
+    const int base = p.inner ? b.nbasei[i] : b.nbase[i];
+    const bool w32 = (p.inner ? b.nwidei[i] : b.nwide[i]) != 0;
     const int4 *nb4 = reinterpret_cast<const int4 *>(p.inner ? b.nbri : b.nbr) + (size_t)i * LPA + lane;
-    pair_passes<L16>(p4, nb4, p.nbr_stride, npl, base, (int)p.ntot, [&](const V4(&pj)[8], const int(&)[8]) {
+    pair_passes(p4, nb4, p.nbr_stride, npl, base, w32, (int)p.ntot, [&](const V4(&pj)[8], const int(&)[8]) {
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const R dx = pj[u].x - pi.x, dy = pj[u].y - pi.y, dz = pj[u].z - pi.z;
@@ -1665,6 +1680,7 @@ __global__ __launch_bounds__(kBlock) void k_permute(Buffers b, Buffers sc, const
   sc.group[i] = b.group[s];
   sc.orig[i] = b.orig[s];
   sc.cell[i] = key[s];
+  sc.nwide[i] = b.nwide[s];  // the form hint of the atom's next list build
   if (b.msx) {
     sc.msx[i] = b.msx[s];
     sc.msy[i] = b.msy[s];
@@ -1735,6 +1751,7 @@ __global__ __launch_bounds__(kBlock) void k_copy_back(Buffers b, Buffers sc) {
   b.group[i] = sc.group[i];
   b.orig[i] = sc.orig[i];
   b.cell[i] = sc.cell[i];
+  b.nwide[i] = sc.nwide[i];
   if (b.msx) {
     b.msx[i] = sc.msx[i];
     b.msy[i] = sc.msy[i];
@@ -1752,21 +1769,24 @@ __global__ __launch_bounds__(kBlock) void k_strain(Params p, Buffers b, const do
   b.z[i] = b.z[i] * factor[r];
 }
 
-// pairs within rc (directed), list entries and pruned-list entries, summed into stat[r][slot][0..2]
+// pairs within rc (directed), list entries, pruned-list entries and atoms with 32-bit lists, summed into
+// stat[r][slot][0..3]
 template <class R>
 __global__ __launch_bounds__(kBlock) void k_count_pairs(Params p, Buffers b) {
   const int64_t tile = blockIdx.x;
   const int r = b.blk_rep[tile];
   const int64_t i = tile * kTile + threadIdx.x;
-  unsigned long long np = 0, ne = 0, nq = 0;
+  unsigned long long np = 0, ne = 0, nq = 0, nw = 0;
   if (b.group[i] != kPad) {
     const int cnt = b.ncount[i];
+    const bool w32 = b.nwide[i] != 0;
     ne = cnt;
     nq = p.inner ? (unsigned long long)b.ncounti[i] : 0ull;
+    nw = w32 ? 1 : 0;
     for (int l = 0; l < p.lpa; ++l) {
-      int j = p.list16 ? b.nbase[i] : 0;  // 16-bit form: steps from the lane's previous entry
+      int j = b.nbase[i];  // 16-bit form: steps from the lane's previous entry
       for (int e = l; e < cnt; e += p.lpa) {
-        if (p.list16) j += reinterpret_cast<const uint16_t *>(b.nbr)[nbr16_index(i, e, p.lpa, p.nbr_stride)];
+        if (!w32) j += reinterpret_cast<const uint16_t *>(b.nbr)[nbr16_index(i, e, p.lpa, p.nbr_stride)];
         else j = b.nbr[nbr_index(i, e, p.lpa, p.nbr_stride)];
         const double d2 = dist2_plain(b.x[j] - b.x[i], b.y[j] - b.y[i], b.z[j] - b.z[i]);
         if (d2 < p.rc2) ++np;
@@ -1777,12 +1797,14 @@ __global__ __launch_bounds__(kBlock) void k_count_pairs(Params p, Buffers b) {
     np += (unsigned long long)shfl_xor_ll((long long)np, o);
     ne += (unsigned long long)shfl_xor_ll((long long)ne, o);
     nq += (unsigned long long)shfl_xor_ll((long long)nq, o);
+    nw += (unsigned long long)shfl_xor_ll((long long)nw, o);
   }
   if ((threadIdx.x & 63) == 0) {
     unsigned long long *row = b.stat + ((size_t)r * kSlots + (blockIdx.x & (kSlots - 1))) * kStat;
     atomicAdd(row, np);
     atomicAdd(row + 1, ne);
     atomicAdd(row + 2, nq);
+    atomicAdd(row + 3, nw);
   }
 }
 
@@ -1823,33 +1845,32 @@ void launch_pos4(const Params &p, const Buffers &b, int precision, hipStream_t s
   else hipLaunchKernelGGL(k_pos4<double>, dim3(tiles(p)), dim3(kBlock), 0, s, p, b);
 }
 
-template <class R, int NM, bool L16, bool PR>
+template <class R, int NM, bool PR>
 static void density_lpa(const Params &p, const Buffers &b, int lpa, int32_t k, hipStream_t s) {
   const unsigned g = (unsigned)(p.ntot * lpa / kBlock);
   switch (lpa) {
-    case 1: hipLaunchKernelGGL((k_density<R, 1, NM, L16, PR>), dim3(g), dim3(kBlock), 0, s, p, b, k); break;
-    case 2: hipLaunchKernelGGL((k_density<R, 2, NM, L16, PR>), dim3(g), dim3(kBlock), 0, s, p, b, k); break;
-    case 4: hipLaunchKernelGGL((k_density<R, 4, NM, L16, PR>), dim3(g), dim3(kBlock), 0, s, p, b, k); break;
-    case 8: hipLaunchKernelGGL((k_density<R, 8, NM, L16, PR>), dim3(g), dim3(kBlock), 0, s, p, b, k); break;
-    default: hipLaunchKernelGGL((k_density<R, 16, NM, L16, PR>), dim3(g), dim3(kBlock), 0, s, p, b, k); break;
+    case 1: hipLaunchKernelGGL((k_density<R, 1, NM, PR>), dim3(g), dim3(kBlock), 0, s, p, b, k); break;
+    case 2: hipLaunchKernelGGL((k_density<R, 2, NM, PR>), dim3(g), dim3(kBlock), 0, s, p, b, k); break;
+    case 4: hipLaunchKernelGGL((k_density<R, 4, NM, PR>), dim3(g), dim3(kBlock), 0, s, p, b, k); break;
+    case 8: hipLaunchKernelGGL((k_density<R, 8, NM, PR>), dim3(g), dim3(kBlock), 0, s, p, b, k); break;
+    default: hipLaunchKernelGGL((k_density<R, 16, NM, PR>), dim3(g), dim3(kBlock), 0, s, p, b, k); break;
   }
 }
 
 template <class R, int NM>
 static void density_form(const Params &p, const Buffers &b, int lpa, int32_t k, hipStream_t s, bool prune) {
-  if (p.list16) (prune ? density_lpa<R, NM, true, true> : density_lpa<R, NM, true, false>)(p, b, lpa, k, s);
-  else (prune ? density_lpa<R, NM, false, true> : density_lpa<R, NM, false, false>)(p, b, lpa, k, s);
+  (prune ? density_lpa<R, NM, true> : density_lpa<R, NM, false>)(p, b, lpa, k, s);
 }
 
-template <class R, int NM, bool L16>
+template <class R, int NM>
 static void force_lpa(const Params &p, const Buffers &b, int lpa, int32_t k, int32_t mode, hipStream_t s) {
   const unsigned g = (unsigned)(p.ntot * lpa / kBlock);
   switch (lpa) {
-    case 1: hipLaunchKernelGGL((k_force<R, 1, NM, L16>), dim3(g), dim3(kBlock), 0, s, p, b, k, mode); break;
-    case 2: hipLaunchKernelGGL((k_force<R, 2, NM, L16>), dim3(g), dim3(kBlock), 0, s, p, b, k, mode); break;
-    case 4: hipLaunchKernelGGL((k_force<R, 4, NM, L16>), dim3(g), dim3(kBlock), 0, s, p, b, k, mode); break;
-    case 8: hipLaunchKernelGGL((k_force<R, 8, NM, L16>), dim3(g), dim3(kBlock), 0, s, p, b, k, mode); break;
-    default: hipLaunchKernelGGL((k_force<R, 16, NM, L16>), dim3(g), dim3(kBlock), 0, s, p, b, k, mode); break;
+    case 1: hipLaunchKernelGGL((k_force<R, 1, NM>), dim3(g), dim3(kBlock), 0, s, p, b, k, mode); break;
+    case 2: hipLaunchKernelGGL((k_force<R, 2, NM>), dim3(g), dim3(kBlock), 0, s, p, b, k, mode); break;
+    case 4: hipLaunchKernelGGL((k_force<R, 4, NM>), dim3(g), dim3(kBlock), 0, s, p, b, k, mode); break;
+    case 8: hipLaunchKernelGGL((k_force<R, 8, NM>), dim3(g), dim3(kBlock), 0, s, p, b, k, mode); break;
+    default: hipLaunchKernelGGL((k_force<R, 16, NM>), dim3(g), dim3(kBlock), 0, s, p, b, k, mode); break;
   }
 }
 
@@ -1857,21 +1878,21 @@ static bool is_al76(const Params &p) { return p.n == 7 && p.m == 6; }
 // kernel form of the potential: 2 tables, 1 Sutton-Chen n = 7 / m = 6, 0 any Sutton-Chen
 static int pot_form(const Params &p) { return p.tab ? 2 : (is_al76(p) ? 1 : 0); }
 
-template <class R, bool L16>
+template <class R>
 static void build_lpa(const Params &p, const Buffers &b, int lpa, int32_t cond, hipStream_t s) {
   const unsigned g = (unsigned)std::min<int64_t>(p.ntot * KB / kBlock, 4096);
   switch (lpa) {
-    case 1: hipLaunchKernelGGL((k_build<R, 1, L16>), dim3(g), dim3(kBlock), 0, s, p, b, cond); break;
-    case 2: hipLaunchKernelGGL((k_build<R, 2, L16>), dim3(g), dim3(kBlock), 0, s, p, b, cond); break;
-    case 4: hipLaunchKernelGGL((k_build<R, 4, L16>), dim3(g), dim3(kBlock), 0, s, p, b, cond); break;
-    case 8: hipLaunchKernelGGL((k_build<R, 8, L16>), dim3(g), dim3(kBlock), 0, s, p, b, cond); break;
-    default: hipLaunchKernelGGL((k_build<R, 16, L16>), dim3(g), dim3(kBlock), 0, s, p, b, cond); break;
+    case 1: hipLaunchKernelGGL((k_build<R, 1>), dim3(g), dim3(kBlock), 0, s, p, b, cond); break;
+    case 2: hipLaunchKernelGGL((k_build<R, 2>), dim3(g), dim3(kBlock), 0, s, p, b, cond); break;
+    case 4: hipLaunchKernelGGL((k_build<R, 4>), dim3(g), dim3(kBlock), 0, s, p, b, cond); break;
+    case 8: hipLaunchKernelGGL((k_build<R, 8>), dim3(g), dim3(kBlock), 0, s, p, b, cond); break;
+    default: hipLaunchKernelGGL((k_build<R, 16>), dim3(g), dim3(kBlock), 0, s, p, b, cond); break;
   }
 }
 
 void launch_build(const Params &p, const Buffers &b, int precision, int lpa, hipStream_t s, int32_t cond) {
-  if (precision) (p.list16 ? build_lpa<float, true> : build_lpa<float, false>)(p, b, lpa, cond, s);
-  else (p.list16 ? build_lpa<double, true> : build_lpa<double, false>)(p, b, lpa, cond, s);
+  if (precision) build_lpa<float>(p, b, lpa, cond, s);
+  else build_lpa<double>(p, b, lpa, cond, s);
 }
 
 void launch_density(const Params &p, const Buffers &b, int precision, int lpa, int32_t k, hipStream_t s,
@@ -1890,12 +1911,12 @@ void launch_density(const Params &p, const Buffers &b, int precision, int lpa, i
 void launch_force(const Params &p, const Buffers &b, int precision, int lpa, int32_t k, int32_t mode,
                   hipStream_t s) {
   switch (pot_form(p) + 3 * (precision ? 1 : 0)) {
-    case 0: (p.list16 ? force_lpa<double, 0, true> : force_lpa<double, 0, false>)(p, b, lpa, k, mode, s); break;
-    case 1: (p.list16 ? force_lpa<double, 1, true> : force_lpa<double, 1, false>)(p, b, lpa, k, mode, s); break;
-    case 2: (p.list16 ? force_lpa<double, 2, true> : force_lpa<double, 2, false>)(p, b, lpa, k, mode, s); break;
-    case 3: (p.list16 ? force_lpa<float, 0, true> : force_lpa<float, 0, false>)(p, b, lpa, k, mode, s); break;
-    case 4: (p.list16 ? force_lpa<float, 1, true> : force_lpa<float, 1, false>)(p, b, lpa, k, mode, s); break;
-    default: (p.list16 ? force_lpa<float, 2, true> : force_lpa<float, 2, false>)(p, b, lpa, k, mode, s); break;
+    case 0: force_lpa<double, 0>(p, b, lpa, k, mode, s); break;
+    case 1: force_lpa<double, 1>(p, b, lpa, k, mode, s); break;
+    case 2: force_lpa<double, 2>(p, b, lpa, k, mode, s); break;
+    case 3: force_lpa<float, 0>(p, b, lpa, k, mode, s); break;
+    case 4: force_lpa<float, 1>(p, b, lpa, k, mode, s); break;
+    default: force_lpa<float, 2>(p, b, lpa, k, mode, s); break;
   }
 }
 

@@ -35,9 +35,7 @@ enum : int {
   E_DRIFT = 8,     // an atom drifted beyond the binning margin before a list build
   E_STATE = 16,    // thermostat: T <= 0 or lambda^2 < 0
   E_SKIN = 32,     // an atom moved more than half the skin since the list build (a trigger was missed)
-  E_WIDE = 64,     // a list entry's offset does not fit the 16-bit list form
-  E_PRUNE = 128,   // an atom moved faster than the pruned lists allow (Control::vb2)
-  E_WIDE_PRUNED = 256  // as E_WIDE, met by a pruning pass
+  E_PRUNE = 128    // an atom moved faster than the pruned lists allow (Control::vb2)
 };
 
 // Device-resident control block (one per system).
@@ -133,7 +131,6 @@ struct Params {
   double tab_inv_drho; // 1 / drho
   int32_t tab_nrho;
   int32_t fold;        // nonzero (mixed form): the density pass does the step's kick-drift (Buffers::pnext)
-  int32_t list16;      // nonzero: the Verlet lists hold 16-bit offsets (nbr16_index), else 32-bit indices
   int32_t inner;       // nonzero: the pair passes read the pruned lists (nbri, ncounti), which the
                        // density pass of each pruning step writes from the full ones
 };
@@ -148,11 +145,14 @@ struct Buffers {
   int32_t *cell;       // linear cell index (within the replica grid) at the last sort
   float *xs, *ys, *zs; // positions at the last sort
   float *xr, *yr, *zr; // positions at the last list build
-  int32_t *nbr;        // Verlet lists, [slot][atom*lpa + lane] (32-bit indices or 16-bit offsets, Params::list16)
+  int32_t *nbr;        // Verlet lists, [slot][atom*lpa + lane]: per atom 16-bit steps or 32-bit indices (nwide)
   int32_t *ncount;     // list length per atom
   int32_t *nbase;      // 16-bit form: the index the atom's first steps count from (its smallest listed neighbour)
-  int32_t *nbri;       // pruned lists (same layout and entry form as nbr)
+  uint8_t *nwide;      // 0: the atom's lists are 16-bit steps; 1, 2: 32-bit indices (2: their span needs them)
+  int32_t *nbri;       // pruned lists (the layout of nbr)
   int32_t *ncounti;    // pruned list length per atom
+  int32_t *nbasei;     // the base and form of each atom's pruned list, as they were at its pruning pass
+  uint8_t *nwidei;     // (a full-list build before the next pruning pass may change nbase and nwide)
   double *eshift;      // Sutton-Chen: the pair-energy shift -n_c Vc - dVc (sum r - n_c rc) over the atom's
                        // pairs within rc, from the density pass (which sums r and n_c for rho's shift)
   int32_t *cell_start; // global cell arrays: [cell_off + c]
@@ -185,18 +185,19 @@ __host__ __device__ inline size_t nbr_index(int64_t i, int e, int lpa, int64_t s
   return ((size_t)(s / kGroup) * (size_t)stride + (size_t)i * lpa + l) * kGroup + (s % kGroup);
 }
 
-// The 16-bit form of the lists: lane l of atom i holds its entries e = l,
-// l + lpa, ... in increasing index order, each as the unsigned step from the
-// lane's previous entry (the first from nbase[i], the smallest index in the
-// atom's list).  Sorted order keeps an atom's neighbours within a few bin
-// layers of it, and one lane's consecutive entries lie lpa entries apart in
-// the atom's sorted list, so a step exceeds a few hundred only where the list
-// moves on to the next bin row or layer: well inside 16 bits at any size
-// whose bin layers hold fewer than 65,535 atoms.  Eight entries to a group
-// per lane, so one 16-byte load gives a lane a whole pass and the pair
-// kernels read half the list bytes.  kOffSentinel (after a lane's last
-// entry) stands for the sentinel index ntot.  A system where a step outgrows
-// 16 bits (a build meets one: E_WIDE) switches to the 32-bit form for good.
+// The 16-bit form of an atom's lists: lane l of atom i holds its entries
+// e = l, l + lpa, ... in increasing index order, each as the unsigned step
+// from the lane's previous entry (the first from nbase[i], the smallest index
+// in the atom's list).  The build keeps this form for every atom whose listed
+// indices span less than 65,535 (all but a few evaporated atoms of the
+// largest cubes: sorted order keeps an atom's neighbours within three or
+// four bin layers of it); then every step between two of them fits, as do
+// those of a pruned list.  Eight entries to a group per lane, so one 16-byte
+// load gives a lane a whole pass and the pair kernels read half the bytes of
+// 32-bit indices.  kOffSentinel (after a lane's last entry) stands for the
+// sentinel index ntot.  The other atoms (Buffers::nwide) hold 32-bit indices
+// (nbr_index) in the same buffer: columns are per atom, and the buffer has
+// room for every atom in that form.
 constexpr int kGroup16 = 8;
 constexpr int kOffSentinel = 0xffff;
 __host__ __device__ inline size_t nbr16_index(int64_t i, int e, int lpa, int64_t stride) {

@@ -122,9 +122,7 @@ struct ptamd_system {
   int chunk = 64;
   int64_t steps_total = 0, sorts = 0, rollbacks = 0, list_builds = 0;
   int64_t nbuild_seen = 0;  // device-side builds already counted in list_builds
-  bool prune = true;        // pruned lists between pruning passes (ptamd_md_params::full_lists == 0)
-  int64_t wide_step = -1;   // step (since creation) at which the lists left the 16-bit form
-  int32_t wide_where = 0;   // 1: a full-list build met a step beyond 16 bits, 2: a pruning pass
+  int prune_every = 1;      // pruning passes every prune_every rebuild points (0: full lists every step)
   double rin = 0.0;         // radius of the last chunk's pruned lists (0: full lists)
   int64_t series_rows = 0;
 };
@@ -187,6 +185,8 @@ static void validate_md(const ptamd_md_params *md) {
   const int l = md->lanes_per_atom;
   if (!(l == 0 || l == 1 || l == 2 || l == 4 || l == 8 || l == 16))
     fail(PTAMD_EINVAL, "lanes_per_atom must be 0 (auto), 1, 2, 4, 8 or 16");
+  if (md->full_lists != 0 && md->full_lists != 1) fail(PTAMD_EINVAL, "full_lists must be 0 or 1");
+  if (md->prune_every < 0 || md->prune_every > 3) fail(PTAMD_EINVAL, "prune_every must be 0 (default), 1, 2 or 3");
 }
 
 // Shift constants of the chosen mode for f(r) = k (a/r)^p: f(rc) and f'(rc).
@@ -211,6 +211,7 @@ static void alloc_buffers(Buffers &b, int64_t ntot, int precision, bool primary)
   // one more entry: the list sentinel (index ntot), parked far away
   b.pos4 = precision ? (void *)dalloc<float4>(ntot + 1) : (void *)dalloc<double4>(ntot + 1);
   b.group = dalloc<uint8_t>(ntot);
+  b.nwide = dalloc<uint8_t>(ntot);  // (the permutation carries the list-form hint)
   b.orig = dalloc<int32_t>(ntot);
   b.cell = dalloc<int32_t>(ntot);
   b.xs = dalloc<float>(ntot); b.ys = dalloc<float>(ntot); b.zs = dalloc<float>(ntot);
@@ -219,6 +220,8 @@ static void alloc_buffers(Buffers &b, int64_t ntot, int precision, bool primary)
     b.ncount = dalloc<int32_t>(ntot);
     b.nbase = dalloc<int32_t>(ntot);
     b.ncounti = dalloc<int32_t>(ntot);
+    b.nbasei = dalloc<int32_t>(ntot);
+    b.nwidei = dalloc<uint8_t>(ntot);
     b.eshift = dalloc<double>(ntot);
     if (precision && ntot <= kFoldMaxAtoms) b.pnext = dalloc<float4>(ntot + 1);  // with the sentinel, as pos4
   }
@@ -226,7 +229,7 @@ static void alloc_buffers(Buffers &b, int64_t ntot, int precision, bool primary)
 
 static void free_buffers(Buffers &b) {
   void *ptrs[] = {b.x, b.y, b.z, b.vx, b.vy, b.vz, b.fx, b.fy, b.fz, b.pos4, b.pnext, b.group, b.orig, b.cell,
-                  b.xs, b.ys, b.zs, b.xr, b.yr, b.zr, b.nbr, b.ncount, b.nbase, b.nbri, b.ncounti, b.eshift, b.cell_start, b.cell_count,
+                  b.xs, b.ys, b.zs, b.xr, b.yr, b.zr, b.nbr, b.ncount, b.nbase, b.nwide, b.nbri, b.ncounti, b.nbasei, b.nwidei, b.eshift, b.cell_start, b.cell_count,
                   b.blk_rep, b.rep, b.acc, b.slots, b.stat, b.series, b.ktime, b.msx, b.msy, b.msz,
                   b.tab_r, b.tab_F};
   for (void *p : ptrs) dfree(p);
@@ -264,10 +267,10 @@ static void alloc_list(ptamd_system *s, int cap) {
   dfree(s->B.nbr);
   dfree(s->B.nbri);
   s->B.nbr = s->B.nbri = nullptr;
-  // 16-bit form: two entries per 32-bit word; the pruned lists have the
-  // same layout and capacity
-  s->B.nbr = dalloc<int32_t>((size_t)s->ntot * cap / (s->P.list16 ? 2 : 1));
-  s->B.nbri = dalloc<int32_t>((size_t)s->ntot * cap / (s->P.list16 ? 2 : 1));
+  // room for every atom's list in the 32-bit form (most use the first half,
+  // two 16-bit entries to a word); the pruned lists have the same layout
+  s->B.nbr = dalloc<int32_t>((size_t)s->ntot * cap);
+  s->B.nbri = dalloc<int32_t>((size_t)s->ntot * cap);
   s->cap = cap;
   s->P.cap_slots = cap / s->lpa;
   invalidate_graphs(s);
@@ -349,7 +352,7 @@ static ptamd_system *create_from_hosts(const std::vector<HostState> &hs, const s
     s->precision = md.precision;
     s->sc = sc;
     s->md = md;
-    s->prune = md.full_lists == 0;
+    s->prune_every = md.full_lists ? 0 : (md.prune_every > 0 ? md.prune_every : 1);
     s->skin = md.skin;
     s->margin = 2.0;
     HIPCHK(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
@@ -427,7 +430,6 @@ static ptamd_system *create_from_hosts(const std::vector<HostState> &hs, const s
     // loop and its update).  Measured: 62,500 atoms +15%, 131,072 atoms +2%;
     // 256,000 atoms -1%, 500,000 atoms -4%, 64 x 13,500 atoms -7%.
     P.fold = (s->precision && s->ntot <= kFoldMaxAtoms) ? 1 : 0;
-    P.list16 = 1;  // until a build meets an offset beyond 16 bits
 
     Buffers &B = s->B;
     alloc_buffers(B, s->ntot, s->precision, true);
@@ -477,6 +479,7 @@ static ptamd_system *create_from_hosts(const std::vector<HostState> &hs, const s
     h2d(s, B.x, hx.data(), 8 * N); h2d(s, B.y, hy.data(), 8 * N); h2d(s, B.z, hz.data(), 8 * N);
     h2d(s, B.vx, hvx.data(), 8 * N); h2d(s, B.vy, hvy.data(), 8 * N); h2d(s, B.vz, hvz.data(), 8 * N);
     h2d(s, B.group, hg.data(), N);
+    HIPCHK(hipMemsetAsync(B.nwide, 0, N, s->stream));  // every list build tries the 16-bit form first
     h2d(s, B.orig, ho.data(), 4 * N);
     h2d(s, B.blk_rep, s->blk_rep_h.data(), 4 * (N / kTile));
     HIPCHK(hipMemsetAsync(B.fx, 0, 8 * N, s->stream));
@@ -626,8 +629,9 @@ static void sort_system(ptamd_system *s) {
 // valid inside the graph without a return to the host.
 static GraphEntry &get_graph(ptamd_system *s, int K, bool with_build, int m) {
   // every launch-time flag captured in the graph is part of its key
-  const int key = 64 * K + (s->P.inner ? 32 : 0) + (m > 1 ? 16 : 0) + (s->P.msum ? 8 : 0) + (s->P.top_free ? 4 : 0) +
-                  (s->P.conv ? 2 : 0) + (with_build ? 1 : 0);
+  const int pe = s->P.inner ? s->prune_every : 0;
+  const int key = 256 * K + 64 * pe + (s->P.inner ? 32 : 0) + (m > 1 ? 16 : 0) + (s->P.msum ? 8 : 0) +
+                  (s->P.top_free ? 4 : 0) + (s->P.conv ? 2 : 0) + (with_build ? 1 : 0);
   auto it = s->graphs.find(key);
   if (it != s->graphs.end()) return it->second;
   GraphEntry g;
@@ -639,12 +643,13 @@ static GraphEntry &get_graph(ptamd_system *s, int K, bool with_build, int m) {
   s->P.trig_v = (fold ? m : m - 1) * 1.5 * s->md.dt_fs;
   HIPCHK(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
   // with pruned lists (Params::inner, only where m > 1) the density passes
-  // of the first step and of every rebuild point prune: a pruned list serves
-  // at most m steps, over which no atom drifts more than m - 1 steps' worth
+  // of the first step and of every pe-th rebuild point prune: a pruned list
+  // serves at most pe m steps, over which no atom drifts more than
+  // pe m - 1 steps' worth
   if (with_build) launch_build(s->P, s->B, s->precision, s->lpa, s->cap_stream);
   for (int32_t k = 0; k < K; ++k) {
     const bool point = k % m == m - 1;
-    const bool prune = k == 0 || point;
+    const bool prune = k == 0 || (point && pe > 0 && ((k + 1) / m) % pe == 0);
     if (fold) {
       if (point) launch_build(s->P, s->B, s->precision, s->lpa, s->cap_stream, 1);
       launch_density(s->P, s->B, s->precision, s->lpa, k, s->cap_stream, prune);
@@ -676,7 +681,7 @@ static int chunk_graph_steps(int K, int nd) {
 // Instantiates every chunk graph a fixed-length burst can launch with the
 // current launch configuration and flags (normal rebuild-point spacing).
 static void prepare_graphs(ptamd_system *s) {
-  s->P.inner = s->prune ? 1 : 0;
+  s->P.inner = s->prune_every > 0 ? 1 : 0;
   for (int g = 1; g <= kMaxChunk; g += (g < 16 ? 1 : 8)) {
     get_graph(s, g, false, kRebuildEvery);
     if (!s->timing) get_graph(s, g, true, kRebuildEvery);
@@ -760,15 +765,9 @@ static void initial_forces(ptamd_system *s) {
   read_ctl(s);
   s->list_builds++;
   s->need_build = false;
-  if (s->h_ctl->err & (E_OVERFLOW | E_WIDE)) {
-    // grow the lists, or widen them to 32-bit indices, and try again from
-    // the same positions
-    if ((s->h_ctl->err & E_WIDE) && s->P.list16) {
-      s->P.list16 = 0;
-      s->wide_step = s->steps_total;
-      s->wide_where = 1;
-    }
-    alloc_list(s, (s->h_ctl->err & E_OVERFLOW) ? s->cap * 3 / 2 : s->cap);
+  if (s->h_ctl->err & E_OVERFLOW) {
+    // grow the lists and try again from the same positions
+    alloc_list(s, s->cap * 3 / 2);
     clear_err(s);
     s->need_sort = true;
     return initial_forces(s);
@@ -849,7 +848,8 @@ static void run_burst(ptamd_system *s, int64_t n_steps, ptamd_averages *out, con
     // fast atoms (hot systems): a rebuild point at every step
     const int m = (kRebuildEvery + 1) * vb <= skin_room ? kRebuildEvery : 1;
     // Pruned lists, used where rebuild points are spaced: a pruning pass keeps
-    // the pairs within rin = rc + 2 (m - 1) dt vs of each other, with vs a
+    // the pairs within rin = rc + 2 (pe m - 1) dt vs of each other (a pruning
+    // pass every pe rebuild points, pe = prune_every), with vs a
     // bound on every atom's speed that each kick checks (E_PRUNE otherwise),
     // so that no pair closer than rc at any step before the next pruning is
     // left out.  2e-3 A covers the FP32 rounding of the coordinates and the
@@ -858,8 +858,8 @@ static void run_burst(ptamd_system *s, int64_t n_steps, ptamd_averages *out, con
     // sample starting from rest does not outrun it as it accelerates.
     {
       const double vs = prune_room * std::max(st.vmax, 0.01 / 1.5);
-      const double rin = s->sc.rc + 2.0 * (m - 1) * s->md.dt_fs * vs + 2e-3;
-      s->P.inner = (m > 1 && s->prune && rin < s->sc.rc + 0.9 * s->skin) ? 1 : 0;
+      const double rin = s->sc.rc + 2.0 * (s->prune_every * m - 1) * s->md.dt_fs * vs + 2e-3;
+      s->P.inner = (m > 1 && s->prune_every > 0 && rin < s->sc.rc + 0.9 * s->skin) ? 1 : 0;
       s->rin = s->P.inner ? rin : 0.0;
       if (s->P.inner) launch_set_prune(s->B, rin * rin, vs * vs, s->stream);
     }
@@ -915,18 +915,12 @@ static void run_burst(ptamd_system *s, int64_t n_steps, ptamd_averages *out, con
     s->list_builds += s->h_ctl->nbuild - s->nbuild_seen;
     s->nbuild_seen = s->h_ctl->nbuild;
     const int err = s->h_ctl->err;
-    if (err & (E_DRIFT | E_OVERFLOW | E_SKIN | E_WIDE | E_WIDE_PRUNED | E_PRUNE)) {
+    if (err & (E_DRIFT | E_OVERFLOW | E_SKIN | E_PRUNE)) {
       // a bound the lists rely on did not hold: re-run the chunk from its start
       snapshot(s, true);
       s->stats_valid = false;
       if (err & E_PRUNE) prune_room *= 1.5;  // for the rest of the burst
-      if ((err & (E_WIDE | E_WIDE_PRUNED)) && s->P.list16) {
-        s->P.list16 = 0;
-        s->wide_step = s->steps_total + step - 1;
-        s->wide_where = (err & E_WIDE) ? 1 : 2;
-      }
-      if (err & (E_OVERFLOW | E_WIDE | E_WIDE_PRUNED))
-        alloc_list(s, (err & E_OVERFLOW) ? s->cap * 3 / 2 : s->cap);
+      if (err & E_OVERFLOW) alloc_list(s, s->cap * 3 / 2);
       clear_err(s);
       s->need_sort = true;
       s->rollbacks++;
@@ -1274,12 +1268,13 @@ static void get_neighbors(ptamd_system *s, int64_t *offsets, int32_t *idx, int64
   initial_forces(s);  // sorts, rebuilds the lists at the current positions
   const int64_t N = s->ntot;
   std::vector<int32_t> o(N), cnt(N), base(N);
-  const bool l16 = s->P.list16 != 0;
-  std::vector<int32_t> nb((size_t)N * s->cap / (l16 ? 2 : 1));
+  std::vector<uint8_t> wide(N);
+  std::vector<int32_t> nb((size_t)N * s->cap);
   d2h(s, o.data(), s->B.orig, 4 * N);
   d2h(s, cnt.data(), s->B.ncount, 4 * N);
   d2h(s, nb.data(), s->B.nbr, nb.size() * 4);
-  if (l16) d2h(s, base.data(), s->B.nbase, 4 * N);
+  d2h(s, base.data(), s->B.nbase, 4 * N);
+  d2h(s, wide.data(), s->B.nwide, N);
   const uint16_t *nb16 = reinterpret_cast<const uint16_t *>(nb.data());
   std::vector<std::vector<int32_t>> rows(s->nreal);
   for (int64_t i = 0; i < N; ++i) {
@@ -1287,9 +1282,9 @@ static void get_neighbors(ptamd_system *s, int64_t *offsets, int32_t *idx, int64
     auto &row = rows[o[i]];
     row.reserve(cnt[i]);
     for (int l = 0; l < s->lpa; ++l) {
-      int32_t j = l16 ? base[i] : 0;  // 16-bit form: steps from the lane's previous entry
+      int32_t j = base[i];  // 16-bit form: steps from the lane's previous entry
       for (int e = l; e < cnt[i]; e += s->lpa) {
-        if (l16) j += nb16[nbr16_index(i, e, s->lpa, s->P.nbr_stride)];
+        if (!wide[i]) j += nb16[nbr16_index(i, e, s->lpa, s->P.nbr_stride)];
         else j = nb[nbr_index(i, e, s->lpa, s->P.nbr_stride)];
         row.push_back(o[j]);
       }
@@ -1334,7 +1329,7 @@ static void get_cells(ptamd_system *s, int32_t *cxyz, double *origin, double *in
   }
 }
 
-static void count_pairs(ptamd_system *s, int64_t *pairs, int64_t *entries, int64_t *pruned) {
+static void count_pairs(ptamd_system *s, int64_t *pairs, int64_t *entries, int64_t *pruned, int64_t *wide) {
   if (s->need_sort) {
     initial_forces(s);  // new lists: no pruned ones yet
     s->P.inner = 0;
@@ -1346,16 +1341,18 @@ static void count_pairs(ptamd_system *s, int64_t *pairs, int64_t *entries, int64
   check_launch();
   d2h(s, s->h_stat, s->B.stat, nst * 8);
   s->stats_valid = false;
-  unsigned long long p = 0, e = 0, q = 0;
+  unsigned long long p = 0, e = 0, q = 0, w = 0;
   for (int r = 0; r < s->n_rep; ++r)
     for (int sl = 0; sl < kSlots; ++sl) {
       p += s->h_stat[((size_t)r * kSlots + sl) * kStat];
       e += s->h_stat[((size_t)r * kSlots + sl) * kStat + 1];
       q += s->h_stat[((size_t)r * kSlots + sl) * kStat + 2];
+      w += s->h_stat[((size_t)r * kSlots + sl) * kStat + 3];
     }
   *pairs = (int64_t)(p / 2);
   *entries = (int64_t)e;
   if (pruned) *pruned = (int64_t)q;
+  if (wide) *wide = (int64_t)w;
 }
 
 // ---------------------------------------------------------------------------
@@ -1377,23 +1374,27 @@ static void reconfigure(ptamd_system *s, int lpa, double skin) {
 struct TuneChoice {
   int lpa;
   double skin;
+  int prune_every;
 };
 static std::map<std::string, TuneChoice> g_tune_cache;
 
 static void autotune(ptamd_system *s, int64_t probe_steps, int use_cache, int *out_lpa, double *out_skin,
-                     double *out_ms) {
+                     int *out_pe, double *out_ms) {
   if (probe_steps < 10) fail(PTAMD_EINVAL, "probe_steps must be >= 10");
-  char keyb[128];
-  std::snprintf(keyb, sizeof keyb, "n%lld-r%d-p%d-rc%.4f-t%d", (long long)s->nreal, s->n_rep, s->precision, s->sc.rc,
-                s->P.tab);
+  const bool may_prune = s->md.full_lists == 0;
+  char keyb[160];
+  std::snprintf(keyb, sizeof keyb, "n%lld-r%d-p%d-rc%.4f-t%d-f%d", (long long)s->nreal, s->n_rep, s->precision,
+                s->sc.rc, s->P.tab, may_prune ? 0 : 1);
   const std::string key(keyb);
   if (use_cache) {
     auto it = g_tune_cache.find(key);
     if (it != g_tune_cache.end()) {
+      s->prune_every = it->second.prune_every;
       reconfigure(s, it->second.lpa, it->second.skin);
       prepare_graphs(s);
       *out_lpa = it->second.lpa;
       *out_skin = it->second.skin;
+      *out_pe = it->second.prune_every;
       *out_ms = 0.0;
       return;
     }
@@ -1411,55 +1412,56 @@ static void autotune(ptamd_system *s, int64_t probe_steps, int use_cache, int *o
   int32_t *save_o = dalloc<int32_t>(N);
   uint8_t *save_g = dalloc<uint8_t>(N);
   double *arr[6] = {s->B.x, s->B.y, s->B.z, s->B.vx, s->B.vy, s->B.vz};
-  const int lpa0 = s->lpa;
-  const double skin0 = s->skin;
-  int best_l = lpa0;
-  double best_s = skin0, best_t = 1e300;
+  const int pe0 = s->prune_every;
+  int best_l = s->lpa, best_pe = pe0;
+  double best_s = s->skin, best_t = 1e300;
+  std::vector<ptamd_averages> tmp(s->n_rep);
+  auto restore = [&] {
+    for (int k = 0; k < 6; ++k) d2d(s, arr[k], save + (size_t)k * N, 8 * N);
+    d2d(s, s->B.orig, save_o, 4 * N);
+    d2d(s, s->B.group, save_g, N);
+    launch_pos4(s->P, s->B, s->precision, s->stream);
+    s->need_sort = true;
+    s->stats_valid = false;
+    sync(s);
+  };
+  // one timed probe burst of a configuration from the saved state, after an
+  // untimed one of the same length (from the same state the probe follows
+  // the same chunk schedule, so every graph it launches is instantiated
+  // there, outside the timed span)
+  auto probe = [&](int lpa, double skin, int pe) {
+    s->prune_every = pe;
+    reconfigure(s, lpa, skin);
+    run_burst(s, probe_steps, tmp.data());
+    restore();
+    HIPCHK(hipEventRecord(s->ev0, s->stream));
+    run_burst(s, probe_steps, tmp.data());
+    HIPCHK(hipEventRecord(s->ev1, s->stream));
+    HIPCHK(hipEventSynchronize(s->ev1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, s->ev0, s->ev1));
+    restore();
+    return (double)ms;
+  };
   try {
     for (int k = 0; k < 6; ++k) d2d(s, save + (size_t)k * N, arr[k], 8 * N);
     d2d(s, save_o, s->B.orig, 4 * N);
     d2d(s, save_g, s->B.group, N);
     sync(s);
+    // stage 1: lanes per atom x skin (at the system's pruning interval);
+    // two rounds over all candidates, each candidate timed by its faster
+    // round: a single probe is noisy enough to flip close choices
     const int lpas[4] = {2, 4, 8, 16};
     // (with pruned lists the skin sets only how often the full lists are
     // built and how many entries each pruning pass reads)
-    const double skins[4] = {0.8, 1.0, 1.5, 2.0};
-    std::vector<ptamd_averages> tmp(s->n_rep);
-    // two rounds over all candidates, each candidate timed by its faster
-    // round: a single probe is noisy enough to flip close choices
+    const double skins[4] = {1.0, 1.5, 2.0, 2.5};
     double tbest[4][4];
     for (auto &row : tbest)
       for (double &t : row) t = 1e300;
     for (int round = 0; round < 2; ++round)
-    for (int li = 0; li < 4; ++li)
-      for (int si = 0; si < 4; ++si) {
-        reconfigure(s, lpas[li], skins[si]);
-        // warm-up with the probe's own length: from the same state the probe
-        // follows the same chunk schedule, so every graph it launches is
-        // instantiated here, outside the timed span
-        run_burst(s, probe_steps, tmp.data());
-        for (int k = 0; k < 6; ++k) d2d(s, arr[k], save + (size_t)k * N, 8 * N);
-        d2d(s, s->B.orig, save_o, 4 * N);
-        d2d(s, s->B.group, save_g, N);
-        launch_pos4(s->P, s->B, s->precision, s->stream);
-        s->need_sort = true;
-        s->stats_valid = false;
-        sync(s);
-        HIPCHK(hipEventRecord(s->ev0, s->stream));
-        run_burst(s, probe_steps, tmp.data());
-        HIPCHK(hipEventRecord(s->ev1, s->stream));
-        HIPCHK(hipEventSynchronize(s->ev1));
-        float ms = 0.f;
-        HIPCHK(hipEventElapsedTime(&ms, s->ev0, s->ev1));
-        tbest[li][si] = std::min(tbest[li][si], (double)ms);
-        for (int k = 0; k < 6; ++k) d2d(s, arr[k], save + (size_t)k * N, 8 * N);
-        d2d(s, s->B.orig, save_o, 4 * N);
-        d2d(s, s->B.group, save_g, N);
-        launch_pos4(s->P, s->B, s->precision, s->stream);
-        s->need_sort = true;
-        s->stats_valid = false;
-        sync(s);
-      }
+      for (int li = 0; li < 4; ++li)
+        for (int si = 0; si < 4; ++si)
+          tbest[li][si] = std::min(tbest[li][si], probe(lpas[li], skins[si], pe0));
     double t_min = 1e300;
     for (auto &row : tbest)
       for (double t : row) t_min = std::min(t_min, t);
@@ -1474,20 +1476,36 @@ static void autotune(ptamd_system *s, int64_t probe_steps, int use_cache, int *o
           best_l = lpas[li];
           best_s = skins[si];
         }
+    // stage 2: the pruning interval (full lists, or a pruning pass every 1,
+    // 2 or 3 rebuild points) for that lanes and skin
+    if (may_prune) {
+      double tp[4] = {1e300, 1e300, 1e300, 1e300};
+      for (int round = 0; round < 2; ++round)
+        for (int pe = 0; pe < 4; ++pe) tp[pe] = std::min(tp[pe], probe(best_l, best_s, pe));
+      best_t = 1e300;
+      for (int pe = 0; pe < 4; ++pe)
+        if (tp[pe] < best_t) {
+          best_t = tp[pe];
+          best_pe = pe;
+        }
+    }
   } catch (...) {
     sync(s);
     dfree(save); dfree(save_o); dfree(save_g);
+    s->prune_every = pe0;
     throw;
   }
   dfree(save); dfree(save_o); dfree(save_g);
+  s->prune_every = best_pe;
   reconfigure(s, best_l, best_s);
   // every chunk graph the next bursts can launch, built now (with the
   // caller's timing setting) rather than inside them
   s->timing = timing_off.was;
   prepare_graphs(s);
-  g_tune_cache[key] = TuneChoice{best_l, best_s};
+  g_tune_cache[key] = TuneChoice{best_l, best_s, best_pe};
   *out_lpa = best_l;
   *out_skin = best_s;
+  *out_pe = best_pe;
   *out_ms = best_t / (double)probe_steps;
 }
 
@@ -1798,10 +1816,9 @@ ptamd_status ptamd_get_info(const ptamd_system *sys, ptamd_info *info) {
     info->steps = sys->steps_total;
     info->skin = sys->skin;
     info->bin_margin = sys->margin;
-    info->list_index_bits = sys->P.list16 ? 16 : 32;
+    info->list_index_bits = 16;
     info->folded = sys->P.fold;
-    info->wide_step = sys->wide_step;
-    info->wide_where = sys->wide_where;
+    info->prune_every = sys->prune_every;
   });
 }
 
@@ -1833,24 +1850,25 @@ ptamd_status ptamd_kernel_timing(ptamd_system *sys, double *avg_ms, double *avg_
 }
 
 ptamd_status ptamd_autotune(ptamd_system *sys, int64_t probe_steps, int32_t use_cache, int32_t *lanes_per_atom,
-                            double *skin, double *ms_per_step) {
+                            double *skin, int32_t *prune_every, double *ms_per_step) {
   return guard([&] {
     use_device(sys);
-    int l = 0;
+    int l = 0, pe = 0;
     double sk = 0.0, ms = 0.0;
-    autotune(sys, probe_steps, use_cache, &l, &sk, &ms);
+    autotune(sys, probe_steps, use_cache, &l, &sk, &pe, &ms);
     if (lanes_per_atom) *lanes_per_atom = l;
     if (skin) *skin = sk;
+    if (prune_every) *prune_every = pe;
     if (ms_per_step) *ms_per_step = ms;
   });
 }
 
 ptamd_status ptamd_count_pairs(ptamd_system *sys, int64_t *pairs_in_rc, int64_t *list_entries,
-                               int64_t *pruned_entries, double *prune_radius) {
+                               int64_t *pruned_entries, double *prune_radius, int64_t *wide_atoms) {
   return guard([&] {
     use_device(sys);
     if (!pairs_in_rc || !list_entries) fail(PTAMD_EINVAL, "NULL argument");
-    count_pairs(sys, pairs_in_rc, list_entries, pruned_entries);
+    count_pairs(sys, pairs_in_rc, list_entries, pruned_entries, wide_atoms);
     if (prune_radius) *prune_radius = sys->rin;
   });
 }

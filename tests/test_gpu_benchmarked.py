@@ -214,6 +214,7 @@ def test_cube50_every_atom_mixed():
         st = g.get_state()
         ser = g.get_series(0, 20)
         fb = g.get_forces()
+        cnt = g.count_pairs()
     _, _, _, group, _ = O.fcc_cube(50, A, True)
     ref = O.forces(st["x"], st["y"], st["z"], p, group)
     n = len(st["x"])
@@ -222,4 +223,4 @@ def test_cube50_every_atom_mixed():
     print(f"\nN={n} mixed, lists of {info['list_index_bits']}-bit entries: forces max {fe:.2e} rms {fr:.2e}, "
           f"U/atom {ue:.2e}")
     assert fe <= 2e-4 and ue <= 1e-5
-    assert info["list_index_bits"] == 16
+    assert info["list_index_bits"] == 16 and cnt["wide_atoms"] == 0

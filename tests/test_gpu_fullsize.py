@@ -53,7 +53,8 @@ def test_autotune_restores_state():
         choice = g.autotune(probe_steps=20, use_cache=False)
         st1 = g.get_state()
         info = g.info()
-    assert choice["lanes_per_atom"] in (2, 4, 8, 16) and choice["skin"] in (0.8, 1.0, 1.5, 2.0)
+    assert choice["lanes_per_atom"] in (2, 4, 8, 16) and choice["skin"] in (1.0, 1.5, 2.0, 2.5)
+    assert choice["prune_every"] in (0, 1, 2, 3) and info["prune_every"] == choice["prune_every"]
     assert info["lanes_per_atom"] == choice["lanes_per_atom"]
     for k in st0:
         assert np.array_equal(st0[k], st1[k])

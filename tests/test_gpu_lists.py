@@ -1,14 +1,15 @@
 """Forms of the Verlet lists and of the step, through the C ABI.
 
-Lists start in the 16-bit form (each entry the step in the sorted order from
-the same lane's previous entry, the first from the smallest index in the
-atom's list); every other GPU test runs on it, and so does the
-500,000-atom cube.  A step beyond 16 bits arises only where a bin layer
-holds more than 65,535 atoms: a system whose build meets one switches to
-32-bit indices for good.  Here a film 20 A thick and 518 A wide, whose bin
-layers hold ~100,000 atoms each, forces that switch; its forces and
-neighbour sets are checked against the oracle on sampled atoms (forces
-relative to max(|F|, F_rms): FP64 1e-9; mixed 2e-4, the parity tests' bar).
+An atom's list is in the 16-bit form (each entry the step in the sorted
+order from the same lane's previous entry, the first from the smallest
+index in the atom's list) unless its listed indices span 65,535 or more;
+then it holds 32-bit indices.  Every other GPU test runs on the 16-bit form,
+and so does the 500,000-atom cube.  Here a film 20 A thick and 518 A wide,
+whose bin layers hold ~100,000 atoms each, puts many atoms in the 32-bit
+form beside others in the 16-bit one; its forces and neighbour sets are
+checked against the oracle on sampled atoms (forces relative to
+max(|F|, F_rms): FP64 1e-9; mixed 2e-4, the parity tests' bar), and a burst
+on pruned lists of both forms runs.
 """
 import numpy as np
 import pytest
@@ -48,7 +49,7 @@ def film():
 
 
 @pytest.mark.parametrize("precision", [0, 1])
-def test_wide_offsets_switch_to_32bit_indices(film, precision):
+def test_wide_atoms_use_32bit_indices(film, precision):
     O = _orc()
     s = film
     md = P.md_params(precision=precision, lanes_per_atom=4)
@@ -56,12 +57,13 @@ def test_wide_offsets_switch_to_32bit_indices(film, precision):
         f = g.compute_forces()
         info = g.info()
         off, idx = g.get_neighbors()
+        cnt = g.count_pairs()
         a = g.run_fast_md(20)[0]
-        info2 = g.info()
-    print(f"\nfilm, precision {precision}: {info['list_index_bits']}-bit lists, "
-          f"{info2['rollbacks']} roll-backs, {info2['list_builds']} builds")
-    assert info["list_index_bits"] == 32 and info2["list_index_bits"] == 32
+        cnt2 = g.count_pairs()
     n = len(s["x"])
+    print(f"\nfilm, precision {precision}: {cnt['wide_atoms']} of {n} atoms with 32-bit lists; after 20 steps "
+          f"{cnt2['wide_atoms']}, pruned entries {cnt2['pruned_entries']}")
+    assert 0 < cnt["wide_atoms"] < n and 0 < cnt2["wide_atoms"] < n
     sample = synth.rng(62).choice(n, size=48, replace=False)
     p = O.sc_params()
     F = np.stack([f["fx"], f["fy"], f["fz"]], 1)
@@ -77,7 +79,6 @@ def test_wide_offsets_switch_to_32bit_indices(film, precision):
         want = want[want != i]
         assert np.array_equal(idx[off[i]:off[i + 1]], want), i
     assert np.isfinite(a["pe"]) and a["n_samples"] == 20
-
 
 
 def test_neighbours_of_a_batch():

@@ -8,7 +8,8 @@ r < rc, so the pruned and the full lists give the same results up to the
 order of summation, and both match the oracle at the parity bars.  Checked
 here:
   - FP64: pruned against full lists and against the oracle over 100 steps
-    (|dr| <= 1e-8 A, |dv| <= 1e-10 A/fs) and 400 steps (to rounding);
+    (|dr| <= 1e-8 A, |dv| <= 1e-10 A/fs) and 400 steps (to rounding), with a
+    pruning pass every 4, 8 or 12 steps;
   - mixed, folded step: pruned against full lists (FP32 rounding);
   - the pruned lists hold every pair within rc at the positions where they
     are read: their size lies between the directed pairs within rc and the
@@ -39,8 +40,8 @@ def _state(nc, noise, T, seed):
     return s
 
 
-def _run(s, n, precision, full, lanes=4, T0=300.0):
-    md = P.md_params(precision=precision, lanes_per_atom=lanes, full_lists=full)
+def _run(s, n, precision, full, lanes=4, T0=300.0, prune_every=0):
+    md = P.md_params(precision=precision, lanes_per_atom=lanes, full_lists=full, prune_every=prune_every)
     with P.System.from_state(s, T0=T0, md=md) as g:
         avg = g.run_fast_md(n)[0]
         st = g.get_state()
@@ -70,6 +71,24 @@ def test_fp64_pruned_matches_full_and_oracle(lanes):
     assert rc < cnt["prune_radius"] < rc + info["skin"]
     assert 2 * cnt["pairs_in_rc"] <= cnt["pruned_entries"] < cnt["list_entries"]
     assert cnt_f["pruned_entries"] == 0 and cnt_f["prune_radius"] == 0.0
+
+
+@pytest.mark.parametrize("prune_every", [2, 3])
+def test_fp64_longer_pruning_intervals(prune_every):
+    O = _orc()
+    s = _state(6, 0.05, 300.0, 55)
+    a_p, st_p, cnt, info = _run(s, 100, 0, 0, prune_every=prune_every)
+    assert info["prune_every"] == prune_every
+    os_ = O.State(*(s[k].copy() for k in ("x", "y", "z", "vx", "vy", "vz", "group")), s["volume0"], s["area0"])
+    ravg, _ = O.run_burst(os_, O.sc_params(), O.md_params(), 100)
+    dr = max(np.abs(st_p[k] - getattr(os_, k)).max() for k in ("x", "y", "z"))
+    dv = max(np.abs(st_p[k] - getattr(os_, k)).max() for k in ("vx", "vy", "vz"))
+    print(f"\nprune every {4 * prune_every} steps: radius {cnt['prune_radius']:.4f} A, pruned {cnt['pruned_entries']}, "
+          f"|dr| {dr:.2e}")
+    assert dr <= 1e-8 and dv <= 1e-10
+    for k in ("ke", "pe", "szz", "tz"):
+        assert a_p[k] == pytest.approx(ravg[k], rel=1e-9, abs=1e-9), k
+    assert 8.1 < cnt["prune_radius"] < 8.1 + info["skin"]
 
 
 def test_fp64_pruned_long_run_to_rounding():
