@@ -873,10 +873,15 @@ __device__ bool build_one(const Params &p, const Buffers &b, int64_t i, int lane
     const double ex = xi - (double)b.xs[i], ey = yi - (double)b.ys[i], ez = zi - (double)b.zs[i];
     if (ex * ex + ey * ey + ez * ez > p.margin2) set_err(b, E_DRIFT);
   }
-  const int dxn = rp.dims[0], dyn = rp.dims[1], dzn = rp.dims[2];
+  // bins in sorted order: axis a2 slowest, a1, then a0 (the stencil rows)
+  const int a0 = rp.ax[0], a1 = rp.ax[1], a2 = rp.ax[2];
+  const int d0n = rp.dims[a0], d1n = rp.dims[a1], d2n = rp.dims[a2];
+  const double pos[3] = {xi, yi, zi};
+  const double p0 = pos[a0], p1 = pos[a1], p2 = pos[a2];
+  const double o0 = rp.origin[a0], o1 = rp.origin[a1], o2 = rp.origin[a2];
   const double hb = p.bin_h;
   const int cl = b.cell[i];
-  const int cx = cl % dxn, cy = (cl / dxn) % dyn, cz = cl / (dxn * dyn);
+  const int c0 = cl % d0n, c1 = (cl / d0n) % d1n, c2 = cl / (d0n * d1n);
   // phase 1: lane l resolves stencil rows l, l + KB, ... into atom ranges
   int rs[NRL], re[NRL];
 #pragma unroll
@@ -884,24 +889,24 @@ __device__ bool build_one(const Params &p, const Buffers &b, int64_t i, int lane
     rs[h2] = re[h2] = 0;
     const int q = lane + h2 * KB;
     if (q >= 25) continue;
-    const int nz = cz + q / 5 - 2, ny = cy + q % 5 - 2;
-    if (nz < 0 || nz >= dzn || ny < 0 || ny >= dyn) continue;
-    const double dz = box_dist(zi, rp.origin[2], hb, nz, dzn), dy = box_dist(yi, rp.origin[1], hb, ny, dyn);
-    const double dyz = dy * dy + dz * dz;
-    if (dyz > p.cull2) continue;
-    int lo = max(cx - 2, 0), hi = min(cx + 2, dxn - 1);
+    const int n2 = c2 + q / 5 - 2, n1 = c1 + q % 5 - 2;
+    if (n2 < 0 || n2 >= d2n || n1 < 0 || n1 >= d1n) continue;
+    const double e2 = box_dist(p2, o2, hb, n2, d2n), e1 = box_dist(p1, o1, hb, n1, d1n);
+    const double e12 = e1 * e1 + e2 * e2;
+    if (e12 > p.cull2) continue;
+    int lo = max(c0 - 2, 0), hi = min(c0 + 2, d0n - 1);
     while (lo <= hi) {
-      const double d = box_dist(xi, rp.origin[0], hb, lo, dxn);
-      if (d * d + dyz <= p.cull2) break;
+      const double d = box_dist(p0, o0, hb, lo, d0n);
+      if (d * d + e12 <= p.cull2) break;
       ++lo;
     }
     while (hi >= lo) {
-      const double d = box_dist(xi, rp.origin[0], hb, hi, dxn);
-      if (d * d + dyz <= p.cull2) break;
+      const double d = box_dist(p0, o0, hb, hi, d0n);
+      if (d * d + e12 <= p.cull2) break;
       --hi;
     }
     if (lo > hi) continue;
-    const int64_t row = rp.cell_off + ((int64_t)nz * dyn + ny) * dxn;
+    const int64_t row = rp.cell_off + ((int64_t)n2 * d1n + n1) * d0n;
     rs[h2] = b.cell_start[row + lo];
     re[h2] = b.cell_start[row + hi] + b.cell_count[row + hi];
   }
@@ -1403,11 +1408,18 @@ __global__ __launch_bounds__(kBlock) void k_chunk_stats(Params p, Buffers b) {
   const int64_t i = tile * kTile + threadIdx.x;
   double d2 = 0.0, v2 = 0.0, l2 = 0.0;
   unsigned long long mn[3] = {~0ull, ~0ull, ~0ull}, mx[3] = {0ull, 0ull, 0ull};
+  long long mom[6] = {0, 0, 0, 0, 0, 0};  // per axis: sum of q and of q^2, q = rint(4 x) (integers: order-free)
   const uint8_t g = b.group[i];
   if (g != kPad) {
     const double x = b.x[i], y = b.y[i], z = b.z[i];
     const double c[3] = {x, y, z};
-    for (int d = 0; d < 3; ++d) mn[d] = mx[d] = okey(c[d]);
+    for (int d = 0; d < 3; ++d) {
+      mn[d] = mx[d] = okey(c[d]);
+      // |x| < 1e4 A (the escape bound): q^2 < 1.6e9, far inside 64 bits over any atom count
+      const long long q = isfinite(c[d]) ? (long long)rint(fmin(fmax(4.0 * c[d], -1e5), 1e5)) : 0;
+      mom[d] = q;
+      mom[3 + d] = q * q;
+    }
     if (moves_z(p, g)) {
       const double ex = x - (double)b.xs[i], ey = y - (double)b.ys[i], ez = z - (double)b.zs[i];
       d2 = ex * ex + ey * ey + ez * ez;
@@ -1428,8 +1440,10 @@ __global__ __launch_bounds__(kBlock) void k_chunk_stats(Params p, Buffers b) {
       mn[d] = min(mn[d], (unsigned long long)shfl_xor_ll((long long)mn[d], o));
       mx[d] = max(mx[d], (unsigned long long)shfl_xor_ll((long long)mx[d], o));
     }
+#pragma unroll
+    for (int d = 0; d < 6; ++d) mom[d] += shfl_xor_ll(mom[d], o);
   }
-  __shared__ unsigned long long sh[kBlock / 64][9];
+  __shared__ unsigned long long sh[kBlock / 64][15];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   if (lane == 0) {
     sh[wid][0] = dbits(d2);
@@ -1439,14 +1453,19 @@ __global__ __launch_bounds__(kBlock) void k_chunk_stats(Params p, Buffers b) {
       sh[wid][5 + d] = mx[d];
     }
     sh[wid][8] = dbits(l2);
+    for (int d = 0; d < 6; ++d) sh[wid][kStatMom + d] = (unsigned long long)mom[d];
   }
   __syncthreads();
-  if (threadIdx.x < 9) {
+  if (threadIdx.x < kStatMom + 6) {
     const int c = threadIdx.x;
     unsigned long long v = sh[0][c];
-    for (int w2 = 1; w2 < kBlock / 64; ++w2) v = (c >= 2 && c < 5) ? min(v, sh[w2][c]) : max(v, sh[w2][c]);
+    for (int w2 = 1; w2 < kBlock / 64; ++w2) {
+      if (c >= kStatMom) v += sh[w2][c];  // two's-complement sums
+      else v = (c >= 2 && c < 5) ? min(v, sh[w2][c]) : max(v, sh[w2][c]);
+    }
     unsigned long long *dst = b.stat + ((size_t)r * kSlots + (blockIdx.x & (kSlots - 1))) * kStat + c;
-    if (c >= 2 && c < 5) atomicMin(dst, v);
+    if (c >= kStatMom) atomicAdd(dst, v);
+    else if (c >= 2 && c < 5) atomicMin(dst, v);
     else atomicMax(dst, v);
   }
 }
@@ -1460,10 +1479,12 @@ __device__ __forceinline__ int cell_coord(double v, double o, double inv_h, int 
 
 __device__ __forceinline__ int atom_cell(const Buffers &b, const RepInfo &rp, int64_t i) {
   if (b.group[i] == kPad) return (int)(rp.ncells - 1);  // virtual last cell: padding sorts to the end
-  const int cx = cell_coord(b.x[i], rp.origin[0], rp.inv_h, rp.dims[0]);
-  const int cy = cell_coord(b.y[i], rp.origin[1], rp.inv_h, rp.dims[1]);
-  const int cz = cell_coord(b.z[i], rp.origin[2], rp.inv_h, rp.dims[2]);
-  return (cz * rp.dims[1] + cy) * rp.dims[0] + cx;
+  int c[3];
+  c[0] = cell_coord(b.x[i], rp.origin[0], rp.inv_h, rp.dims[0]);
+  c[1] = cell_coord(b.y[i], rp.origin[1], rp.inv_h, rp.dims[1]);
+  c[2] = cell_coord(b.z[i], rp.origin[2], rp.inv_h, rp.dims[2]);
+  const int a0 = rp.ax[0], a1 = rp.ax[1], a2 = rp.ax[2];
+  return (c[a2] * rp.dims[a1] + c[a1]) * rp.dims[a0] + c[a0];
 }
 
 // One atomic per distinct cell in a wave (atoms arrive nearly sorted, so a

@@ -60,6 +60,7 @@ struct Control {
 };
 
 constexpr int kStat = 16;  // u64 entries per statistics row
+constexpr int kStatMom = 9;  // first of the six position-moment columns (sum of q and of q^2 per axis, q = rint(4 x))
 
 // Per-replica constants and grid (device memory, read by kernels).
 struct RepInfo {
@@ -72,6 +73,11 @@ struct RepInfo {
   double inv_h;         // 1 / bin edge
   int32_t dims[3];
   int32_t pad1;
+  // sorted order of the bins: axis ax[2] slowest, then ax[1], ax[0] fastest
+  // (stencil rows run along ax[0]); the axis of widest spread goes slowest,
+  // so that a bin layer holds as few atoms as the sample's shape allows
+  int32_t ax[3];
+  int32_t pad2;
   int64_t cell_off;     // offset of this replica's cells in the global cell arrays
   int64_t ncells;       // dims product (+1 virtual cell for padding atoms)
   double center[3];     // nominal cube centre (escape test)

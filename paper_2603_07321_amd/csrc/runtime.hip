@@ -66,6 +66,7 @@ struct RepHost {
   double origin[3] = {0, 0, 0};
   double inv_h = 0;
   int dims[3] = {1, 1, 1};
+  int ax[3] = {0, 1, 2};  // bin order: ax[2] slowest, ax[0] fastest
   int64_t cell_off = 0, ncells = 0;
   double nom_lo[3] = {0, 0, 0}, nom_hi[3] = {0, 0, 0};  // extent of the sample at creation (strain 0)
 };
@@ -253,6 +254,7 @@ static void upload_reps(ptamd_system *s) {
       d.origin[k] = h.origin[k];
       d.dims[k] = h.dims[k];
       d.center[k] = h.center[k];
+      d.ax[k] = h.ax[k];
     }
     d.inv_h = h.inv_h;
     d.cell_off = h.cell_off;
@@ -539,6 +541,33 @@ static void read_stats(ptamd_system *s, int64_t n_stamps = 0) {
   s->stats_valid = true;
 }
 
+// Order of a replica's bins for the next sort: the axis along which its
+// atoms spread widest (variance from the integer position moments of the
+// last statistics pass) goes slowest, so that a layer of bins, and with it
+// the span of sorted indices an atom's neighbours occupy, holds as few atoms
+// as the sample's shape allows (a cube that melts and flows out sideways
+// between its held z faces piles its atoms into the middle z layers).  An
+// axis takes another's place only when its spread is 20% wider, so that the
+// order does not flip back and forth; a cube keeps x fastest, z slowest.
+static void choose_axis_order(ptamd_system *s, int r) {
+  RepHost &rh = s->reps[r];
+  long long m1[3] = {0, 0, 0}, m2[3] = {0, 0, 0};
+  for (int sl = 0; sl < kSlots; ++sl)
+    for (int d = 0; d < 3; ++d) {
+      m1[d] += (long long)s->h_stat[((size_t)r * kSlots + sl) * kStat + kStatMom + d];
+      m2[d] += (long long)s->h_stat[((size_t)r * kSlots + sl) * kStat + kStatMom + 3 + d];
+    }
+  const double n = (double)std::max<int64_t>(rh.nreal, 1);
+  double var[3];
+  for (int d = 0; d < 3; ++d) var[d] = (double)m2[d] / n - ((double)m1[d] / n) * ((double)m1[d] / n);
+  int order[3] = {rh.ax[0], rh.ax[1], rh.ax[2]};
+  // slowest axis first, then the middle one, each kept unless beaten by 20%
+  for (int pos = 2; pos >= 1; --pos)
+    for (int q = pos - 1; q >= 0; --q)
+      if (var[order[q]] > 1.2 * var[order[pos]]) std::swap(order[q], order[pos]);
+  for (int d = 0; d < 3; ++d) rh.ax[d] = order[d];
+}
+
 // Grid of each replica from the bounding box of the last statistics pass,
 // then a counting sort of the atoms by cell (atoms of a cell by original
 // index), and the permutation of every per-atom array.
@@ -581,6 +610,7 @@ static void sort_system(ptamd_system *s) {
     rh.cell_off = cells;
     rh.ncells = nc + 1;  // + virtual cell for the padding
     cells += rh.ncells;
+    choose_axis_order(s, r);
   }
   if (cells > s->cells_cap) {
     sync(s);
@@ -1316,9 +1346,10 @@ static void get_cells(ptamd_system *s, int32_t *cxyz, double *origin, double *in
     if (o[i] < 0) continue;
     const RepHost &rh = s->reps[rep_of[i]];
     const int cl = c[i];
-    cxyz[3 * (int64_t)o[i]] = cl % rh.dims[0];
-    cxyz[3 * (int64_t)o[i] + 1] = (cl / rh.dims[0]) % rh.dims[1];
-    cxyz[3 * (int64_t)o[i] + 2] = cl / (rh.dims[0] * rh.dims[1]);
+    const int d0 = rh.dims[rh.ax[0]], d1 = rh.dims[rh.ax[1]];
+    cxyz[3 * (int64_t)o[i] + rh.ax[0]] = cl % d0;
+    cxyz[3 * (int64_t)o[i] + rh.ax[1]] = (cl / d0) % d1;
+    cxyz[3 * (int64_t)o[i] + rh.ax[2]] = cl / (d0 * d1);
   }
   for (int r = 0; r < s->n_rep; ++r) {
     for (int d = 0; d < 3; ++d) {

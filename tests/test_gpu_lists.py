@@ -1,15 +1,20 @@
-"""Forms of the Verlet lists and of the step, through the C ABI.
+"""Forms of the Verlet lists, the order of the bins, and the step, through
+the C ABI.
 
 An atom's list is in the 16-bit form (each entry the step in the sorted
 order from the same lane's previous entry, the first from the smallest
 index in the atom's list) unless its listed indices span 65,535 or more;
-then it holds 32-bit indices.  Every other GPU test runs on the 16-bit form,
-and so does the 500,000-atom cube.  Here a film 20 A thick and 518 A wide,
-whose bin layers hold ~100,000 atoms each, puts many atoms in the 32-bit
-form beside others in the 16-bit one; its forces and neighbour sets are
-checked against the oracle on sampled atoms (forces relative to
-max(|F|, F_rms): FP64 1e-9; mixed 2e-4, the parity tests' bar), and a burst
-on pruned lists of both forms runs.
+then it holds 32-bit indices.  Bins are sorted with the axis of widest
+spread slowest, so that a layer of bins holds as few atoms as the sample's
+shape allows.  Checked here:
+  - a 1,048,576-atom cube (64^3 cells), whose z layers of bins hold ~26,500
+    atoms each, puts part of its atoms in the 32-bit form beside others in
+    the 16-bit one; forces and neighbour sets against the oracle on sampled
+    atoms (forces relative to max(|F|, F_rms): FP64 1e-9; mixed 2e-4, the
+    parity tests' bar), and a burst on pruned lists of both forms runs;
+  - a film 20 A thick and 518 A wide: its bins are ordered along a wide
+    axis, so every atom keeps the 16-bit form; cells (bit-exact) and lists
+    against the oracle.
 """
 import numpy as np
 import pytest
@@ -48,10 +53,29 @@ def film():
     return synth.fcc_slab(128, 128, 5, 0.05, 61)  # 327,680 atoms, 20 A thick
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_wide_atoms_use_32bit_indices(film, precision):
+def _sampled_checks(s, f, off, idx, skin, precision, seed):
     O = _orc()
-    s = film
+    n = len(s["x"])
+    sample = synth.rng(seed).choice(n, size=32, replace=False)
+    p = O.sc_params()
+    F = np.stack([f["fx"], f["fy"], f["fz"]], 1)
+    ref = np.stack([O.atom_force(s["x"], s["y"], s["z"], p, int(i)) for i in sample])
+    frms = np.sqrt((ref ** 2).sum(1).mean())
+    err = (np.linalg.norm(F[sample] - ref, axis=1) / np.maximum(np.linalg.norm(ref, axis=1), frms)).max()
+    print(f"sampled forces: {err:.2e}")
+    assert err <= (1e-9 if precision == 0 else 2e-4)
+    rl = p.rc + skin
+    for i in sample[:12]:
+        d2 = (s["x"] - s["x"][i]) ** 2 + (s["y"] - s["y"][i]) ** 2 + (s["z"] - s["z"][i]) ** 2
+        want = np.flatnonzero(d2 < rl * rl)
+        want = want[want != i]
+        assert np.array_equal(idx[off[i]:off[i + 1]], want), i
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("precision", [0, 1])
+def test_wide_atoms_use_32bit_indices(precision):
+    s = synth.cube_state(64, 0.05, 0.0, 61)  # 1,048,576 atoms
     md = P.md_params(precision=precision, lanes_per_atom=4)
     with P.System.from_state(s, T0=300.0, md=md) as g:
         f = g.compute_forces()
@@ -61,23 +85,30 @@ def test_wide_atoms_use_32bit_indices(film, precision):
         a = g.run_fast_md(20)[0]
         cnt2 = g.count_pairs()
     n = len(s["x"])
-    print(f"\nfilm, precision {precision}: {cnt['wide_atoms']} of {n} atoms with 32-bit lists; after 20 steps "
+    print(f"\ncube of {n} atoms, precision {precision}: {cnt['wide_atoms']} with 32-bit lists; after 20 steps "
           f"{cnt2['wide_atoms']}, pruned entries {cnt2['pruned_entries']}")
     assert 0 < cnt["wide_atoms"] < n and 0 < cnt2["wide_atoms"] < n
-    sample = synth.rng(62).choice(n, size=48, replace=False)
-    p = O.sc_params()
-    F = np.stack([f["fx"], f["fy"], f["fz"]], 1)
-    ref = np.stack([O.atom_force(s["x"], s["y"], s["z"], p, int(i)) for i in sample])
-    frms = np.sqrt((ref ** 2).sum(1).mean())
-    err = (np.linalg.norm(F[sample] - ref, axis=1) / np.maximum(np.linalg.norm(ref, axis=1), frms)).max()
-    print(f"sampled forces: {err:.2e}")
-    assert err <= (1e-9 if precision == 0 else 2e-4)
-    rl = p.rc + info["skin"]
-    for i in sample[:16]:
-        d2 = (s["x"] - s["x"][i]) ** 2 + (s["y"] - s["y"][i]) ** 2 + (s["z"] - s["z"][i]) ** 2
-        want = np.flatnonzero(d2 < rl * rl)
-        want = want[want != i]
-        assert np.array_equal(idx[off[i]:off[i + 1]], want), i
+    _sampled_checks(s, f, off, idx, info["skin"], precision, 62)
+    assert np.isfinite(a["pe"]) and a["n_samples"] == 20
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_film_bins_follow_its_wide_axes(film, precision):
+    O = _orc()
+    s = film
+    md = P.md_params(precision=precision, lanes_per_atom=4)
+    with P.System.from_state(s, T0=300.0, md=md) as g:
+        f = g.compute_forces()
+        info = g.info()
+        off, idx = g.get_neighbors()
+        cnt = g.count_pairs()
+        cxyz, origin, inv_h, dims = g.get_cells()
+        a = g.run_fast_md(20)[0]
+    print(f"\nfilm, precision {precision}: {cnt['wide_atoms']} atoms with 32-bit lists, grid {dims[0]}")
+    assert cnt["wide_atoms"] == 0
+    rc = O.cell_assign(s["x"], s["y"], s["z"], origin[0], inv_h[0], dims[0])
+    assert np.array_equal(cxyz, rc)
+    _sampled_checks(s, f, off, idx, info["skin"], precision, 63)
     assert np.isfinite(a["pe"]) and a["n_samples"] == 20
 
 
