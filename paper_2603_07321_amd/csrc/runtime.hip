@@ -116,7 +116,11 @@ struct ptamd_system {
   bool timing = false;
   double t_ev_ms = 0.0;   // the same launches bracketed by HIP events (includes dispatch latency)
   double wall_khz = 1e5;  // device wall-clock rate
-  hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;  // autotuner probes
+  // kernel timing: created without the system-scope fence at recording
+  // (timing only), which would add a cache writeback and invalidation to
+  // every bracketed launch
+  hipEvent_t tev0 = nullptr, tev1 = nullptr, tev2 = nullptr;
   double t_den_ms = 0.0;  // density launches bracketed by HIP events
   double t_sum_ms = 0.0;
   int64_t t_count = 0;
@@ -360,7 +364,9 @@ static ptamd_system *create_from_hosts(const std::vector<HostState> &hs, const s
     HIPCHK(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
     HIPCHK(hipEventCreate(&s->ev0));
     HIPCHK(hipEventCreate(&s->ev1));
-    HIPCHK(hipEventCreate(&s->ev2));
+    HIPCHK(hipEventCreateWithFlags(&s->tev0, hipEventDisableSystemFence));
+    HIPCHK(hipEventCreateWithFlags(&s->tev1, hipEventDisableSystemFence));
+    HIPCHK(hipEventCreateWithFlags(&s->tev2, hipEventDisableSystemFence));
     {
       int khz = 0;
       HIPCHK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, s->device));
@@ -515,7 +521,9 @@ static ptamd_system *create_from_hosts(const std::vector<HostState> &hs, const s
     if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
     if (s->ev0) (void)hipEventDestroy(s->ev0);
     if (s->ev1) (void)hipEventDestroy(s->ev1);
-  if (s->ev2) (void)hipEventDestroy(s->ev2);
+    if (s->tev0) (void)hipEventDestroy(s->tev0);
+    if (s->tev1) (void)hipEventDestroy(s->tev1);
+    if (s->tev2) (void)hipEventDestroy(s->tev2);
     delete s;
     throw;
   }
@@ -928,13 +936,13 @@ static void run_burst(ptamd_system *s, int64_t n_steps, ptamd_averages *out, con
       for (int k = 0; k < nd; ++k) {
         const bool timed = k == nd - 1 && nd == 2;
         if (!s->P.fold) launch_kick_drift(s->P, s->B, s->precision, k, 0, s->stream);
-        if (timed) HIPCHK(hipEventRecord(s->ev0, s->stream));
+        if (timed) HIPCHK(hipEventRecord(s->tev0, s->stream));
         launch_density(s->P, s->B, s->precision, s->lpa, k, s->stream, k == 0);
-        if (timed) HIPCHK(hipEventRecord(s->ev1, s->stream));
+        if (timed) HIPCHK(hipEventRecord(s->tev1, s->stream));
         Params pt = s->P;
         pt.ktime = timed ? 1 : 0;
         launch_force(pt, s->B, s->precision, s->lpa, k, (s->P.fold && m == 1 && k == nd - 1) ? 2 : 0, s->stream);
-        if (timed) HIPCHK(hipEventRecord(s->ev2, s->stream));
+        if (timed) HIPCHK(hipEventRecord(s->tev2, s->stream));
       }
       done = nd;
       if (K > nd) launch_set_base(s->B, step + nd, s->stream);
@@ -969,9 +977,9 @@ static void run_burst(ptamd_system *s, int64_t n_steps, ptamd_averages *out, con
     }
     if (timing && nd == 2) {
       float ms = 0.f;
-      HIPCHK(hipEventElapsedTime(&ms, s->ev0, s->ev1));
+      HIPCHK(hipEventElapsedTime(&ms, s->tev0, s->tev1));
       s->t_den_ms += ms;
-      HIPCHK(hipEventElapsedTime(&ms, s->ev1, s->ev2));
+      HIPCHK(hipEventElapsedTime(&ms, s->tev1, s->tev2));
       s->t_ev_ms += ms;
       // the stamps were folded into the control block with the statistics
       s->t_sum_ms += (double)(s->h_ctl->kt_last - s->h_ctl->kt_first) / s->wall_khz;
@@ -1554,7 +1562,9 @@ static void destroy(ptamd_system *s) {
   if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
   if (s->ev0) (void)hipEventDestroy(s->ev0);
   if (s->ev1) (void)hipEventDestroy(s->ev1);
-  if (s->ev2) (void)hipEventDestroy(s->ev2);
+  if (s->tev0) (void)hipEventDestroy(s->tev0);
+  if (s->tev1) (void)hipEventDestroy(s->tev1);
+  if (s->tev2) (void)hipEventDestroy(s->tev2);
   delete s;
 }
 
