@@ -859,16 +859,14 @@ template <class R> __device__ __forceinline__ float4 to_f4(typename V4T<R>::T v)
 // slots, if the listed indices span 65,535 or more (the caller then builds
 // the 32-bit form): every step between two of them then fits 16 bits, and so
 // do the steps of any subset, such as the pruned list.
-template <class R, int LPA>
-__device__ bool build_one(const Params &p, const Buffers &b, int64_t i, int lane, bool w32) {
-  using V4 = typename V4T<R>::T;
-  const int r = b.blk_rep[i / kTile];
-  const V4 *p4 = reinterpret_cast<const V4 *>(b.pos4);
-  const RepInfo &rp = b.rep[r];
-  const double xi = b.x[i], yi = b.y[i], zi = b.z[i];
-  // in the gather copies' coordinates (the FP32 prefilter)
-  const float4 pi = make_float4((float)(R)(xi - gorigin<R>(rp, 0)), (float)(R)(yi - gorigin<R>(rp, 1)),
-                                (float)(R)(zi - gorigin<R>(rp, 2)), 0.f);
+// Phase 1 of a build: lane l of the atom's KB resolves stencil rows l,
+// l + KB, ... into ranges of sorted atoms [rs, re), trimmed to the bins whose
+// box lies within the culling radius of the atom (an empty range otherwise).
+// Also checks the atom's drift since the sort against the margin.
+template <class R>
+__device__ __forceinline__ void stencil_rows(const Params &p, const Buffers &b, int64_t i, int lane,
+                                             const RepInfo &rp, double xi, double yi, double zi, int (&rs)[NRL],
+                                             int (&re)[NRL]) {
   if (lane == 0) {
     const double ex = xi - (double)b.xs[i], ey = yi - (double)b.ys[i], ez = zi - (double)b.zs[i];
     if (ex * ex + ey * ey + ez * ez > p.margin2) set_err(b, E_DRIFT);
@@ -882,8 +880,6 @@ __device__ bool build_one(const Params &p, const Buffers &b, int64_t i, int lane
   const double hb = p.bin_h;
   const int cl = b.cell[i];
   const int c0 = cl % d0n, c1 = (cl / d0n) % d1n, c2 = cl / (d0n * d1n);
-  // phase 1: lane l resolves stencil rows l, l + KB, ... into atom ranges
-  int rs[NRL], re[NRL];
 #pragma unroll
   for (int h2 = 0; h2 < NRL; ++h2) {
     rs[h2] = re[h2] = 0;
@@ -910,6 +906,35 @@ __device__ bool build_one(const Params &p, const Buffers &b, int64_t i, int lane
     rs[h2] = b.cell_start[row + lo];
     re[h2] = b.cell_start[row + hi] + b.cell_count[row + hi];
   }
+}
+
+// The rows' ranges of the q-th stencil row, from the lane that resolved it.
+__device__ __forceinline__ void row_range(int q, int gbase, const int (&rs)[NRL], const int (&re)[NRL], int *s0,
+                                          int *e0) {
+  const int src = gbase + (q % KB);
+  int rq = rs[0], eq = re[0];
+#pragma unroll
+  for (int h2 = 1; h2 < NRL; ++h2)
+    if (q >= h2 * KB) {
+      rq = rs[h2];
+      eq = re[h2];
+    }
+  *s0 = __shfl(rq, src);
+  *e0 = __shfl(eq, src);
+}
+
+template <class R, int LPA>
+__device__ bool build_one(const Params &p, const Buffers &b, int64_t i, int lane, bool w32) {
+  using V4 = typename V4T<R>::T;
+  const int r = b.blk_rep[i / kTile];
+  const V4 *p4 = reinterpret_cast<const V4 *>(b.pos4);
+  const RepInfo &rp = b.rep[r];
+  const double xi = b.x[i], yi = b.y[i], zi = b.z[i];
+  // in the gather copies' coordinates (the FP32 prefilter)
+  const float4 pi = make_float4((float)(R)(xi - gorigin<R>(rp, 0)), (float)(R)(yi - gorigin<R>(rp, 1)),
+                                (float)(R)(zi - gorigin<R>(rp, 2)), 0.f);
+  int rs[NRL], re[NRL];
+  stencil_rows<R>(p, b, i, lane, rp, xi, yi, zi, rs, re);
   // phase 2: scan the rows in order, KB x KCH candidates per pass.  All
   // KCH positions are loaded before any is tested, and every lane tests its
   // candidates with the same FP32 arithmetic (no branch the compiler could
@@ -935,16 +960,8 @@ __device__ bool build_one(const Params &p, const Buffers &b, int64_t i, int lane
   __shared__ int ring[kBlock / KB][64];
   int *rg = ring[threadIdx.x / KB];
   for (int q = 0; q < 25; ++q) {
-    const int src = gbase + (q % KB);
-    int rq = rs[0], eq = re[0];
-#pragma unroll
-    for (int h2 = 1; h2 < NRL; ++h2)
-      if (q >= h2 * KB) {
-        rq = rs[h2];
-        eq = re[h2];
-      }
-    const int s0 = __shfl(rq, src);
-    const int e0 = __shfl(eq, src);
+    int s0, e0;
+    row_range(q, gbase, rs, re, &s0, &e0);
     for (int t = s0; t < e0; t += KB * KCH) {
       int jc[KCH];
       float4 qv[KCH];
@@ -1041,6 +1058,135 @@ __global__ __launch_bounds__(kBlock) void k_build(Params p, Buffers b, int32_t c
       const bool w32 = b.nwide[i] == 2;
       if (!build_one<R, LPA>(p, b, i, lane, w32)) build_one<R, LPA>(p, b, i, lane, true);
     }
+}
+
+// Staged build.  The candidate scan only filters: each kept index goes, at
+// its ballot-prefix position (the order of build_one), to the atom's buffer
+// in LDS (Params::cap_slots * LPA words, the list's capacity).  Once the
+// scan is over, the atom's lanes write the list from there in whole 16-byte
+// groups, in the 16-bit form if the indices kept span less than 65,535 and
+// as 32-bit indices otherwise; so no attempt is redone, and the per-candidate
+// work is the filter, a ballot and at most one LDS store.  Same lists as
+// build_one, entry for entry.
+template <class R, int LPA>
+__device__ void build_staged(const Params &p, const Buffers &b, int64_t i, int lane, int *buf) {
+  using V4 = typename V4T<R>::T;
+  const int r = b.blk_rep[i / kTile];
+  const V4 *p4 = reinterpret_cast<const V4 *>(b.pos4);
+  const RepInfo &rp = b.rep[r];
+  const double xi = b.x[i], yi = b.y[i], zi = b.z[i];
+  const float4 pi = make_float4((float)(R)(xi - gorigin<R>(rp, 0)), (float)(R)(yi - gorigin<R>(rp, 1)),
+                                (float)(R)(zi - gorigin<R>(rp, 2)), 0.f);
+  int rs[NRL], re[NRL];
+  stencil_rows<R>(p, b, i, lane, rp, xi, yi, zi, rs, re);
+  const int gbase = (threadIdx.x & 63) & ~(KB - 1);
+  const unsigned below = (1u << lane) - 1u;
+  const int cap = p.cap_slots * LPA;
+  const int self = (int)i;
+  int cnt = 0;
+  for (int q = 0; q < 25; ++q) {
+    int s0, e0;
+    row_range(q, gbase, rs, re, &s0, &e0);
+    for (int t = s0; t < e0; t += KB * KCH) {
+      int jc[KCH];
+      float4 qv[KCH];
+#pragma unroll
+      for (int u = 0; u < KCH; ++u) {
+        jc[u] = t + u * KB + lane;
+        qv[u] = to_f4<R>(gather<V4>(p4, min(jc[u], e0 - 1)));
+      }
+#pragma unroll
+      for (int u = 0; u < KCH; ++u) {
+        const int j = jc[u];
+        const float dx = qv[u].x - pi.x, dy = qv[u].y - pi.y, dz = qv[u].z - pi.z;
+        const float d2 = dx * dx + dy * dy + dz * dz;
+        bool ok = (j < e0) & (j != self) & (d2 <= p.rlist2_hi);
+        // near rlist the FP64 plain formula (no contraction) decides, with the
+        // oracle's rounding; the FP32 copy settles candidates away from it
+        if (ok && !(d2 < p.rlist2_lo))
+          ok = dist2_plain(sub_plain(b.x[j], xi), sub_plain(b.y[j], yi), sub_plain(b.z[j], zi)) < p.rlist2;
+        const unsigned m = (unsigned)(__ballot(ok) >> gbase) & ((1u << KB) - 1u);
+        const int pos = cnt + __popc(m & below);
+        if (ok && pos < cap) buf[pos] = j;
+        cnt += __popc(m);
+      }
+    }
+  }
+  // (a wavefront's LDS accesses take effect in program order: only the
+  // compiler is held back)
+  __builtin_amdgcn_wave_barrier();
+  asm volatile("" ::: "memory");
+  const bool over = cnt > cap;  // cnt is the same in all KB lanes (ballot counts)
+  const int n = over ? cap : cnt;
+  // kept in increasing index order: the span is the last minus the first
+  const int base = n > 0 ? buf[0] : self;
+  const bool w32 = n > 0 && buf[n - 1] - base >= kOffSentinel;
+  const int padded = (n + kPass * LPA - 1) / (kPass * LPA) * (kPass * LPA);
+  int4 *out = reinterpret_cast<int4 *>(b.nbr);
+  if (!w32) {
+    // group g: lane l = g % LPA of pass row = g / LPA, its eight entries
+    for (int g = lane; g < padded / kGroup16; g += KB) {
+      const int row = g / LPA, l = g % LPA;
+      const int e0 = row * kGroup16 * LPA + l;
+      int prev = row == 0 ? base : buf[e0 - LPA];
+      unsigned v[kGroup16];
+#pragma unroll
+      for (int s = 0; s < kGroup16; ++s) {
+        const int e = e0 + s * LPA;
+        if (e < n) {
+          const int j = buf[e];
+          v[s] = (unsigned)(j - prev);
+          prev = j;
+        } else {
+          v[s] = (unsigned)kOffSentinel;
+        }
+      }
+      out[(size_t)row * p.nbr_stride + (size_t)i * LPA + l] =
+          make_int4((int)(v[0] | (v[1] << 16)), (int)(v[2] | (v[3] << 16)), (int)(v[4] | (v[5] << 16)),
+                    (int)(v[6] | (v[7] << 16)));
+    }
+  } else {
+    // group g: lane l = g % LPA, slots 4 (g / LPA) .. 4 (g / LPA) + 3
+    for (int g = lane; g < padded / kGroup; g += KB) {
+      const int sg = g / LPA, l = g % LPA;
+      int v[kGroup];
+#pragma unroll
+      for (int s = 0; s < kGroup; ++s) {
+        const int e = (sg * kGroup + s) * LPA + l;
+        v[s] = e < n ? buf[e] : (int)p.ntot;
+      }
+      out[(size_t)sg * p.nbr_stride + (size_t)i * LPA + l] = make_int4(v[0], v[1], v[2], v[3]);
+    }
+  }
+  if (lane == 0) {
+    if (over) set_err(b, E_OVERFLOW);
+    b.ncount[i] = n;
+    b.nbase[i] = base;
+    b.nwide[i] = w32 ? 2 : 0;
+    b.xr[i] = (float)xi;
+    b.yr[i] = (float)yi;
+    b.zr[i] = (float)zi;
+  }
+  // the buffer is reused by the atom's lanes for their next atom
+  __builtin_amdgcn_wave_barrier();
+  asm volatile("" ::: "memory");
+}
+
+// The staged build's kernel: dynamic LDS of kBlock / KB buffers of
+// Params::cap_slots * LPA words (launched where that fits kStageLdsMax).
+constexpr int kStageLdsMax = 64 * 1024;
+template <class R, int LPA>
+__global__ __launch_bounds__(kBlock) void k_build_staged(Params p, Buffers b, int32_t cond) {
+  if (cond) {
+    if (b.ctl->rebuild == 0) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(reinterpret_cast<unsigned long long *>(&b.ctl->nbuild), 1ull);
+  }
+  extern __shared__ int stage[];
+  const int lane = (int)(threadIdx.x & (KB - 1));
+  int *buf = stage + (size_t)(threadIdx.x / KB) * (size_t)(p.cap_slots * LPA);
+  const int64_t per_pass = (int64_t)gridDim.x * (kBlock / KB);
+  for (int64_t i = (int64_t)blockIdx.x * (kBlock / KB) + threadIdx.x / KB; i < p.ntot; i += per_pass)
+    if (b.group[i] != kPad) build_staged<R, LPA>(p, b, i, lane, buf);  // a lane group skips together
 }
 
 // In the mixed form (p.fold) the step's kick-drift is done here too.  The
@@ -1902,6 +2048,18 @@ static int pot_form(const Params &p) { return p.tab ? 2 : (is_al76(p) ? 1 : 0); 
 template <class R>
 static void build_lpa(const Params &p, const Buffers &b, int lpa, int32_t cond, hipStream_t s) {
   const unsigned g = (unsigned)std::min<int64_t>(p.ntot * KB / kBlock, 4096);
+  const size_t lds = (size_t)(kBlock / KB) * (size_t)p.cap_slots * (size_t)lpa * sizeof(int);
+  if (lds <= (size_t)kStageLdsMax) {
+    switch (lpa) {
+      case 1: hipLaunchKernelGGL((k_build_staged<R, 1>), dim3(g), dim3(kBlock), lds, s, p, b, cond); break;
+      case 2: hipLaunchKernelGGL((k_build_staged<R, 2>), dim3(g), dim3(kBlock), lds, s, p, b, cond); break;
+      case 4: hipLaunchKernelGGL((k_build_staged<R, 4>), dim3(g), dim3(kBlock), lds, s, p, b, cond); break;
+      case 8: hipLaunchKernelGGL((k_build_staged<R, 8>), dim3(g), dim3(kBlock), lds, s, p, b, cond); break;
+      default: hipLaunchKernelGGL((k_build_staged<R, 16>), dim3(g), dim3(kBlock), lds, s, p, b, cond); break;
+    }
+    return;
+  }
+  // lists too long to stage: the direct build
   switch (lpa) {
     case 1: hipLaunchKernelGGL((k_build<R, 1>), dim3(g), dim3(kBlock), 0, s, p, b, cond); break;
     case 2: hipLaunchKernelGGL((k_build<R, 2>), dim3(g), dim3(kBlock), 0, s, p, b, cond); break;
