@@ -105,6 +105,16 @@ template <class V4> __device__ __forceinline__ V4 gather(const V4 *base, int j) 
   return *reinterpret_cast<const V4 *>(reinterpret_cast<const char *>(base) + off);
 }
 
+// The same, coordinates only (w undefined): the density passes need no B',
+// and a 12-byte FP32 gather returns a quarter fewer bytes through the vector
+// memory data path, which the pair passes keep busy.
+template <class V4> __device__ __forceinline__ V4 gather_xyz(const V4 *base, int j) { return gather<V4>(base, j); }
+template <> __device__ __forceinline__ float4 gather_xyz<float4>(const float4 *base, int j) {
+  const unsigned off = (unsigned)j * (unsigned)sizeof(float4);
+  const float3 v = *reinterpret_cast<const float3 *>(reinterpret_cast<const char *>(base) + off);
+  return make_float4(v.x, v.y, v.z, 0.f);
+}
+
 // Origin of the pair kernels' gather copies (pos4, pnext) of a replica's
 // positions: the FP32 copies of the mixed form hold coordinates relative to
 // the cube's centre, so that their rounding (half an ulp of the coordinate)
@@ -122,27 +132,37 @@ template <class R> __device__ __forceinline__ double gorigin(const RepInfo &rp, 
 // hides behind this pass's arithmetic.  The scheduling barriers keep that
 // issue order.  (Gathering the next pass's positions ahead as well, into a
 // second buffer, measured slower on the 62,500-atom cube.)  body(pj, jv)
-// evaluates eight gathered entries; jv holds their indices (the pruning
-// density pass writes them into the pruned list).  An atom's list is in one
-// of two forms (Buffers::nwide): 16-bit (w32 false), one 16-byte group of
-// eight entries per pass, each entry the step from the lane's previous index
-// (from the atom's base for its first), kOffSentinel the sentinel (only ever
-// after the last real entry of a lane, so the running index may run on past
-// it); or 32-bit indices, two groups of four per pass.
-template <class V4, class Body>
-__device__ __forceinline__ void pair_passes(const V4 *p4, const int4 *nb4, int64_t stride, int npl, int base,
-                                            bool w32, int sent, Body &&body) {
+// evaluates eight gathered entries (XYZ: coordinates only); jv holds their
+// indices (the pruning density pass writes them into the pruned list).  An
+// atom's list is in one of two forms (Buffers::nwide): 16-bit (w32 false),
+// one 16-byte group of eight entries per pass, each entry the step from the
+// lane's previous index (from the atom's base for its first), kOffSentinel
+// the sentinel (only ever after the last real entry of a lane, so the
+// running index may run on past it); or 32-bit indices, two groups of four
+// per pass.  The lane holds nreal real entries.  Decoding takes one of three wave-uniform paths: no atom of
+// the wavefront has 32-bit lists and every lane's pass is all real entries
+// (every pass but the last one or two: no sentinel test); no 32-bit lists;
+// or both forms.
+template <bool XYZ, class V4, class Body>
+__device__ __forceinline__ void pair_passes(const V4 *p4, const int4 *nb4, int64_t stride, int npl, int nreal,
+                                            int base, bool w32, int sent, Body &&body) {
   V4 pj[8];
   int jv[8];
   int jp = base;
+  const bool any_w32 = __ballot(w32) != 0ull;
   int4 la = nb4[0], lb = la;
-  if (w32) lb = nb4[stride];
+  if (any_w32 && w32) lb = nb4[stride];
   for (int s = 0; s < npl; s += kPass) {
-    if (w32) {
-      jv[0] = la.x; jv[1] = la.y; jv[2] = la.z; jv[3] = la.w;
-      jv[4] = lb.x; jv[5] = lb.y; jv[6] = lb.z; jv[7] = lb.w;
+    const unsigned w[4] = {(unsigned)la.x, (unsigned)la.y, (unsigned)la.z, (unsigned)la.w};
+    if (!any_w32 && __ballot(s + kPass > nreal) == 0ull) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        jp += (int)(w[u] & 0xffffu);
+        jv[2 * u] = jp;
+        jp += (int)(w[u] >> 16);
+        jv[2 * u + 1] = jp;
+      }
     } else {
-      const unsigned w[4] = {(unsigned)la.x, (unsigned)la.y, (unsigned)la.z, (unsigned)la.w};
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const unsigned lo = w[u] & 0xffffu, hi = w[u] >> 16;
@@ -151,13 +171,17 @@ __device__ __forceinline__ void pair_passes(const V4 *p4, const int4 *nb4, int64
         jp += (int)hi;
         jv[2 * u + 1] = hi == (unsigned)kOffSentinel ? sent : jp;
       }
+      if (any_w32 && w32) {
+        jv[0] = la.x; jv[1] = la.y; jv[2] = la.z; jv[3] = la.w;
+        jv[4] = lb.x; jv[5] = lb.y; jv[6] = lb.z; jv[7] = lb.w;
+      }
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) pj[u] = gather<V4>(p4, jv[u]);
+    for (int u = 0; u < 8; ++u) pj[u] = XYZ ? gather_xyz<V4>(p4, jv[u]) : gather<V4>(p4, jv[u]);
     __builtin_amdgcn_sched_barrier(0);
     if (s + kPass < npl) {
       const size_t row = (size_t)((s + kPass) / kPass);  // the next pass
-      if (w32) {
+      if (any_w32 && w32) {
         la = nb4[(2 * row) * stride];
         lb = nb4[(2 * row + 1) * stride];
       } else {
@@ -167,6 +191,25 @@ __device__ __forceinline__ void pair_passes(const V4 *p4, const int4 *nb4, int64
     __builtin_amdgcn_sched_barrier(0);
     body(pj, jv);
   }
+}
+
+// Real entries of lane `lane` of an atom with cnt list entries (entry e is
+// at lane e % LPA).
+template <int LPA> __device__ __forceinline__ int lane_entries(int cnt, int lane) {
+  return cnt > lane ? (cnt - lane + LPA - 1) / LPA : 0;
+}
+
+// Workgroups go to the eight XCDs in turn (workgroup b to XCD b % 8), and
+// each XCD has an L2 of its own.  The pair kernels take their atoms by this
+// remapped index, so that each XCD works through one contiguous eighth of
+// the sorted atoms, whose neighbours' positions then stay in its L2, instead
+// of every eighth block across the whole system.  A bijection on
+// [0, gridDim.x) for any grid size.
+constexpr unsigned kXcd = 8;
+__device__ __forceinline__ int64_t xcd_block() {
+  const unsigned nb = gridDim.x, b = blockIdx.x;
+  const unsigned x = b % kXcd, q = nb / kXcd, r = nb % kXcd;
+  return (int64_t)(x * q + min(x, r) + b / kXcd);
 }
 
 // Pruned lists.  The pruning density pass keeps, of every pass of the full
@@ -1202,18 +1245,19 @@ __global__ __launch_bounds__(kBlock) void k_build_staged(Params p, Buffers b, in
 // PR: a pruning pass (Params::inner): it walks the full list and writes the
 // pruned one (the entries within rin, Control::rin2), which the pair passes
 // of the following steps, up to the next pruning pass, read instead.
-template <class R, int LPA, int NM, bool PR>
+template <class R, int LPA, int NM, bool PR, bool FOLD>
 __global__ __launch_bounds__(kBlock) void k_density(Params p, Buffers b, int32_t k) {
   using V4 = typename V4T<R>::T;
-  const int64_t gt = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t blk = xcd_block();
+  const int64_t gt = blk * kBlock + threadIdx.x;
   const int64_t i = gt / LPA;
   const int lane = (int)(gt & (LPA - 1));
-  const int64_t tile = ((int64_t)blockIdx.x * (kBlock / LPA)) / kTile;
+  const int64_t tile = (blk * (kBlock / LPA)) / kTile;
   const int r = b.blk_rep[tile];
   const int64_t step = b.ctl->base + k;
   const int par = (int)(step & 1);
-  const bool fold = p.fold && step >= 1;
-  if (!p.fold) {
+  const bool fold = FOLD && step >= 1;
+  if (!FOLD) {
     // the slots of the other parity were consumed by this step's kick-drift
     // (in the mixed form the force pass clears them: this pass reads them)
     const size_t nz = (size_t)p.n_rep * kSlots * kNQ;
@@ -1249,7 +1293,8 @@ __global__ __launch_bounds__(kBlock) void k_density(Params p, Buffers b, int32_t
     const bool full = PR || !p.inner;
     // slots per lane: the list is padded with the far-away sentinel to whole
     // passes, so every slot of a pass holds a valid index
-    const int npl = pass_slots<LPA>((full ? b.ncount : b.ncounti)[i]);
+    const int cnt = (full ? b.ncount : b.ncounti)[i];
+    const int npl = pass_slots<LPA>(cnt);
     const int base = full ? b.nbase[i] : b.nbasei[i];
     const bool w32 = (full ? b.nwide[i] : b.nwidei[i]) != 0;
     const int4 *nb4 = reinterpret_cast<const int4 *>(full ? b.nbr : b.nbri) + (size_t)i * LPA + lane;
@@ -1259,7 +1304,7 @@ __global__ __launch_bounds__(kBlock) void k_density(Params p, Buffers b, int32_t
       __shared__ int ring[PR ? 2 * kPass * kBlock : 1];
       pw.init(ring, base, w32);
     }
-    pair_passes(pn, nb4, p.nbr_stride, npl, base, w32, (int)p.ntot, [&](const V4(&pj)[8], const int(&jv)[8]) {
+    pair_passes<true>(pn, nb4, p.nbr_stride, npl, lane_entries<LPA>(cnt, lane), base, w32, (int)p.ntot, [&](const V4(&pj)[8], const int(&jv)[8]) {
       bool keep[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
@@ -1293,7 +1338,7 @@ __global__ __launch_bounds__(kBlock) void k_density(Params p, Buffers b, int32_t
     }
   }
   if (fold) {
-    const int64_t a0 = (int64_t)blockIdx.x * (kBlock / LPA);  // the block's first atom
+    const int64_t a0 = blk * (kBlock / LPA);  // the block's first atom
     const bool first = a0 % kTile == 0 && (tile == 0 || b.blk_rep[tile - 1] != r);
     const StepStart st = start_lambda(p, b, r, step, first, 0, qk);
     // a replica whose averages converged at this step's sample keeps its
@@ -1339,18 +1384,19 @@ __global__ __launch_bounds__(kBlock) void k_density(Params p, Buffers b, int32_t
 // force pass: mode 0 = step (second half kick + sums), 1 = forces only,
 // 2 = step, and the next step is a list rebuild point of the mixed form
 // ---------------------------------------------------------------------------
-template <class R, int LPA, int NM>
+template <class R, int LPA, int NM, bool FOLD>
 __global__ __launch_bounds__(kBlock) void k_force(Params p, Buffers b, int32_t k, int32_t mode) {
   using V4 = typename V4T<R>::T;
   const unsigned long long t_begin = p.ktime ? wall_clock64() : 0ull;
-  const int64_t gt = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t blk = xcd_block();
+  const int64_t gt = blk * kBlock + threadIdx.x;
   const int64_t i = gt / LPA;
   const int lane = (int)(gt & (LPA - 1));
-  const int64_t tile = ((int64_t)blockIdx.x * (kBlock / LPA)) / kTile;
+  const int64_t tile = (blk * (kBlock / LPA)) / kTile;
   const int r = b.blk_rep[tile];
   const int64_t step = b.ctl->base + k;
   const int par = (int)(step & 1);
-  if (p.fold) {
+  if (FOLD) {
     // mixed form: the slots of the other parity were read by this step's
     // density pass (its kick-drift part); the next step's adds into them
     const size_t nz = (size_t)p.n_rep * kSlots * kNQ;
@@ -1365,7 +1411,7 @@ __global__ __launch_bounds__(kBlock) void k_force(Params p, Buffers b, int32_t k
   double x = 0.0, y = 0.0, z = 0.0, vx = 0.0, vy = 0.0, vz = 0.0;
   if (real && lane == 0) {
     z = b.z[i];
-    if (p.fold) {
+    if (FOLD) {
       x = b.x[i]; y = b.y[i];
       vx = b.vx[i]; vy = b.vy[i]; vz = b.vz[i];
     }
@@ -1380,9 +1426,9 @@ __global__ __launch_bounds__(kBlock) void k_force(Params p, Buffers b, int32_t k
   // force's rounding by at most the cube's half height.
   // Sutton-Chen, with w_j = -m B'_j from the density pass:
   //   dU/dr = [-n eps (a/r)^n + (w_i + w_j) (a/r)^m] / r - (dVc - (w_i + w_j) drhoc / m)
-  // and the pair energy V - Vc - (r - rc) dVc summed as sum(-n V) here and
-  // the shift, which the density pass formed from its sums of r and of the
-  // pairs.  Tables: B' as is.
+  // and the pair energy V - Vc - (r - rc) dVc summed as sum(-n V) here (as
+  // sum (a/r)^n for n = 7, m = 6) and the shift, which the density pass
+  // formed from its sums of r and of the pairs.  Tables: B' as is.
   R fx = 0, fy = 0, fz = 0, ep = 0;
   if (real) {
     const V4 pi = p4[i];
@@ -1391,11 +1437,12 @@ __global__ __launch_bounds__(kBlock) void k_force(Params p, Buffers b, int32_t k
     const R dVc = (R)p.dVc, dm = (R)(p.drhoc / p.m);
     // slots per lane: the list is padded with the far-away sentinel to whole
     // passes, so every slot of a pass holds a valid index
-    const int npl = pass_slots<LPA>((p.inner ? b.ncounti : b.ncount)[i]);
+    const int cnt = (p.inner ? b.ncounti : b.ncount)[i];
+    const int npl = pass_slots<LPA>(cnt);
     const int base = p.inner ? b.nbasei[i] : b.nbase[i];
     const bool w32 = (p.inner ? b.nwidei[i] : b.nwide[i]) != 0;
     const int4 *nb4 = reinterpret_cast<const int4 *>(p.inner ? b.nbri : b.nbr) + (size_t)i * LPA + lane;
-    pair_passes(p4, nb4, p.nbr_stride, npl, base, w32, (int)p.ntot, [&](const V4(&pj)[8], const int(&)[8]) {
+    pair_passes<false>(p4, nb4, p.nbr_stride, npl, lane_entries<LPA>(cnt, lane), base, w32, (int)p.ntot, [&](const V4(&pj)[8], const int(&)[8]) {
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const R dx = pj[u].x - pi.x, dy = pj[u].y - pi.y, dz = pj[u].z - pi.z;
@@ -1416,6 +1463,16 @@ __global__ __launch_bounds__(kBlock) void k_force(Params p, Buffers b, int32_t k
             const R V = rphi * rinv;
             f = ((drphi - V) * rinv + (pi.w + pj[u].w) * drho) * rinv;
             ep += V;
+          } else if (NM == 1) {
+            // n = m + 1: ws t^m - n eps t^n = (ws - n eps t) t^m, and the
+            // energy sums t^n (eps applied once per atom)
+            const R t = a * rinv, t2 = t * t;
+            const R t6 = t2 * t2 * t2;
+            const R ws = pi.w + pj[u].w;
+            const R C = (neps * t + ws) * t6;
+            const R D = dVc - ws * dm;
+            f = (C * rinv - D) * rinv;
+            ep += t6 * t;
           } else {
             R tn, tm;
             sc_powers<R, NM>(a * rinv, p.n, p.m, &tn, &tm);
@@ -1448,7 +1505,7 @@ __global__ __launch_bounds__(kBlock) void k_force(Params p, Buffers b, int32_t k
     b.fz[i] = Fz;
     if (!isfinite(Fx + Fy + Fz)) set_err(b, E_NONFINITE);
     if (moves_z(p, g)) {
-      if (!p.fold) {
+      if (!FOLD) {
         vx = b.vx[i];
         vy = b.vy[i];
         vz = b.vz[i];
@@ -1466,7 +1523,7 @@ __global__ __launch_bounds__(kBlock) void k_force(Params p, Buffers b, int32_t k
       q[Q_MV2] = to_fix(p.mvv2e_m * (vx * vx + vy * vy + vz * vz));
       q[Q_MVZ2] = to_fix(p.mvv2e_m * vz * vz);
     }
-    if (p.fold) {
+    if (FOLD) {
       // mixed form: where the next step's drift takes the atom, for the next
       // density pass (forces only: a burst's first step, lambda 1); and,
       // before a rebuild point, whether the lists last until the one after
@@ -1479,8 +1536,9 @@ __global__ __launch_bounds__(kBlock) void k_force(Params p, Buffers b, int32_t k
           atomicOr(&b.ctl->rebuild, 1);
       }
     }
-    // pair energy of the atom: tables sum V; Sutton-Chen sums -n V, plus the shift
-    const double epair = (NM == 2) ? (double)ep : -(double)ep / p.n + eshift;
+    // pair energy of the atom: tables sum V; Sutton-Chen sums -n V (n = 7,
+    // m = 6: (a/r)^n, that is V / eps), plus the shift
+    const double epair = (NM == 2) ? (double)ep : (NM == 1 ? p.eps * (double)ep : -(double)ep / p.n) + eshift;
     q[Q_EPAIR] = to_fix(0.5 * epair);
     q[Q_WZZ] = to_fix((z - zc) * Fz);
     if (g == 2) q[Q_RZ] = to_fix(-Fz);
@@ -2012,33 +2070,52 @@ void launch_pos4(const Params &p, const Buffers &b, int precision, hipStream_t s
   else hipLaunchKernelGGL(k_pos4<double>, dim3(tiles(p)), dim3(kBlock), 0, s, p, b);
 }
 
-template <class R, int NM, bool PR>
+// FOLD: the folded step (Params::fold), which exists in the mixed form only;
+// its kernels are separate instances, so the others hold no registers for it.
+template <class R, int NM, bool PR, bool FOLD>
 static void density_lpa(const Params &p, const Buffers &b, int lpa, int32_t k, hipStream_t s) {
   const unsigned g = (unsigned)(p.ntot * lpa / kBlock);
   switch (lpa) {
-    case 1: hipLaunchKernelGGL((k_density<R, 1, NM, PR>), dim3(g), dim3(kBlock), 0, s, p, b, k); break;
-    case 2: hipLaunchKernelGGL((k_density<R, 2, NM, PR>), dim3(g), dim3(kBlock), 0, s, p, b, k); break;
-    case 4: hipLaunchKernelGGL((k_density<R, 4, NM, PR>), dim3(g), dim3(kBlock), 0, s, p, b, k); break;
-    case 8: hipLaunchKernelGGL((k_density<R, 8, NM, PR>), dim3(g), dim3(kBlock), 0, s, p, b, k); break;
-    default: hipLaunchKernelGGL((k_density<R, 16, NM, PR>), dim3(g), dim3(kBlock), 0, s, p, b, k); break;
+    case 1: hipLaunchKernelGGL((k_density<R, 1, NM, PR, FOLD>), dim3(g), dim3(kBlock), 0, s, p, b, k); break;
+    case 2: hipLaunchKernelGGL((k_density<R, 2, NM, PR, FOLD>), dim3(g), dim3(kBlock), 0, s, p, b, k); break;
+    case 4: hipLaunchKernelGGL((k_density<R, 4, NM, PR, FOLD>), dim3(g), dim3(kBlock), 0, s, p, b, k); break;
+    case 8: hipLaunchKernelGGL((k_density<R, 8, NM, PR, FOLD>), dim3(g), dim3(kBlock), 0, s, p, b, k); break;
+    default: hipLaunchKernelGGL((k_density<R, 16, NM, PR, FOLD>), dim3(g), dim3(kBlock), 0, s, p, b, k); break;
   }
 }
 
 template <class R, int NM>
 static void density_form(const Params &p, const Buffers &b, int lpa, int32_t k, hipStream_t s, bool prune) {
-  (prune ? density_lpa<R, NM, true> : density_lpa<R, NM, false>)(p, b, lpa, k, s);
+  if constexpr (sizeof(R) == sizeof(float)) {
+    if (p.fold) {
+      (prune ? density_lpa<R, NM, true, true> : density_lpa<R, NM, false, true>)(p, b, lpa, k, s);
+      return;
+    }
+  }
+  (prune ? density_lpa<R, NM, true, false> : density_lpa<R, NM, false, false>)(p, b, lpa, k, s);
+}
+
+template <class R, int NM, bool FOLD>
+static void force_fold(const Params &p, const Buffers &b, int lpa, int32_t k, int32_t mode, hipStream_t s) {
+  const unsigned g = (unsigned)(p.ntot * lpa / kBlock);
+  switch (lpa) {
+    case 1: hipLaunchKernelGGL((k_force<R, 1, NM, FOLD>), dim3(g), dim3(kBlock), 0, s, p, b, k, mode); break;
+    case 2: hipLaunchKernelGGL((k_force<R, 2, NM, FOLD>), dim3(g), dim3(kBlock), 0, s, p, b, k, mode); break;
+    case 4: hipLaunchKernelGGL((k_force<R, 4, NM, FOLD>), dim3(g), dim3(kBlock), 0, s, p, b, k, mode); break;
+    case 8: hipLaunchKernelGGL((k_force<R, 8, NM, FOLD>), dim3(g), dim3(kBlock), 0, s, p, b, k, mode); break;
+    default: hipLaunchKernelGGL((k_force<R, 16, NM, FOLD>), dim3(g), dim3(kBlock), 0, s, p, b, k, mode); break;
+  }
 }
 
 template <class R, int NM>
 static void force_lpa(const Params &p, const Buffers &b, int lpa, int32_t k, int32_t mode, hipStream_t s) {
-  const unsigned g = (unsigned)(p.ntot * lpa / kBlock);
-  switch (lpa) {
-    case 1: hipLaunchKernelGGL((k_force<R, 1, NM>), dim3(g), dim3(kBlock), 0, s, p, b, k, mode); break;
-    case 2: hipLaunchKernelGGL((k_force<R, 2, NM>), dim3(g), dim3(kBlock), 0, s, p, b, k, mode); break;
-    case 4: hipLaunchKernelGGL((k_force<R, 4, NM>), dim3(g), dim3(kBlock), 0, s, p, b, k, mode); break;
-    case 8: hipLaunchKernelGGL((k_force<R, 8, NM>), dim3(g), dim3(kBlock), 0, s, p, b, k, mode); break;
-    default: hipLaunchKernelGGL((k_force<R, 16, NM>), dim3(g), dim3(kBlock), 0, s, p, b, k, mode); break;
+  if constexpr (sizeof(R) == sizeof(float)) {
+    if (p.fold) {
+      force_fold<R, NM, true>(p, b, lpa, k, mode, s);
+      return;
+    }
   }
+  force_fold<R, NM, false>(p, b, lpa, k, mode, s);
 }
 
 static bool is_al76(const Params &p) { return p.n == 7 && p.m == 6; }
