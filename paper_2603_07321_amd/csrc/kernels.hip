@@ -1112,7 +1112,7 @@ __global__ __launch_bounds__(kBlock) void k_build(Params p, Buffers b, int32_t c
 // work is the filter, a ballot and at most one LDS store.  Same lists as
 // build_one, entry for entry.
 template <class R, int LPA>
-__device__ void build_staged(const Params &p, const Buffers &b, int64_t i, int lane, int *buf) {
+__device__ void build_staged(const Params &p, const Buffers &b, int64_t i, int lane, int *buf, int *rowtab) {
   using V4 = typename V4T<R>::T;
   const int r = b.blk_rep[i / kTile];
   const V4 *p4 = reinterpret_cast<const V4 *>(b.pos4);
@@ -1126,33 +1126,71 @@ __device__ void build_staged(const Params &p, const Buffers &b, int64_t i, int l
   const unsigned below = (1u << lane) - 1u;
   const int cap = p.cap_slots * LPA;
   const int self = (int)i;
+  // The 25 row ranges as one sequence of candidates c = 0 .. T - 1: row q
+  // holds c in [P_q, P_q+1) and candidate c of it is atom c + (rs_q - P_q).
+  // The scan takes KB x KCH consecutive candidates per pass whatever rows
+  // they fall in, instead of a pass per row (rows average fewer candidates
+  // than a pass holds).  P and the offsets go to LDS (tab: P at 0 .. 25,
+  // offsets at 32 .. 56); lane l resolved rows l and l + KB.
+  int len[NRL];
+#pragma unroll
+  for (int h2 = 0; h2 < NRL; ++h2) len[h2] = re[h2] - rs[h2];
+  int tot = 0;
+  int *tab = rowtab + (threadIdx.x / KB) * 64;
+#pragma unroll
+  for (int h2 = 0; h2 < NRL; ++h2) {
+    int incl = len[h2];
+#pragma unroll
+    for (int o = 1; o < KB; o <<= 1) {
+      const int up = __shfl_up(incl, o, KB);
+      if (lane >= o) incl += up;
+    }
+    const int q = lane + h2 * KB;
+    const int start = tot + incl - len[h2];
+    if (q < 25) {
+      tab[q] = start;
+      tab[32 + q] = rs[h2] - start;
+    }
+    tot += __shfl(incl, gbase + KB - 1);
+  }
+  if (lane == 0) tab[25] = tot;
+  __builtin_amdgcn_wave_barrier();
+  asm volatile("" ::: "memory");
+  // this lane's row, the next row's start and the offset (its candidates
+  // only move forward)
+  int k = 0, pn = tab[1], off = tab[32];
   int cnt = 0;
-  for (int q = 0; q < 25; ++q) {
-    int s0, e0;
-    row_range(q, gbase, rs, re, &s0, &e0);
-    for (int t = s0; t < e0; t += KB * KCH) {
-      int jc[KCH];
-      float4 qv[KCH];
+  for (int c0 = 0; c0 < tot; c0 += KB * KCH) {
+    int jc[KCH];
+    bool in[KCH];
 #pragma unroll
-      for (int u = 0; u < KCH; ++u) {
-        jc[u] = t + u * KB + lane;
-        qv[u] = to_f4<R>(gather<V4>(p4, min(jc[u], e0 - 1)));
+    for (int u = 0; u < KCH; ++u) {
+      const int c = c0 + u * KB + lane;
+      while (k < 24 && c >= pn) {
+        ++k;
+        pn = tab[k + 1];
+        off = tab[32 + k];
       }
+      in[u] = c < tot;
+      jc[u] = in[u] ? c + off : self;
+    }
+    float4 qv[KCH];
 #pragma unroll
-      for (int u = 0; u < KCH; ++u) {
-        const int j = jc[u];
-        const float dx = qv[u].x - pi.x, dy = qv[u].y - pi.y, dz = qv[u].z - pi.z;
-        const float d2 = dx * dx + dy * dy + dz * dz;
-        bool ok = (j < e0) & (j != self) & (d2 <= p.rlist2_hi);
-        // near rlist the FP64 plain formula (no contraction) decides, with the
-        // oracle's rounding; the FP32 copy settles candidates away from it
-        if (ok && !(d2 < p.rlist2_lo))
-          ok = dist2_plain(sub_plain(b.x[j], xi), sub_plain(b.y[j], yi), sub_plain(b.z[j], zi)) < p.rlist2;
-        const unsigned m = (unsigned)(__ballot(ok) >> gbase) & ((1u << KB) - 1u);
-        const int pos = cnt + __popc(m & below);
-        if (ok && pos < cap) buf[pos] = j;
-        cnt += __popc(m);
-      }
+    for (int u = 0; u < KCH; ++u) qv[u] = to_f4<R>(gather<V4>(p4, jc[u]));
+#pragma unroll
+    for (int u = 0; u < KCH; ++u) {
+      const int j = jc[u];
+      const float dx = qv[u].x - pi.x, dy = qv[u].y - pi.y, dz = qv[u].z - pi.z;
+      const float d2 = dx * dx + dy * dy + dz * dz;
+      bool ok = in[u] & (j != self) & (d2 <= p.rlist2_hi);
+      // near rlist the FP64 plain formula (no contraction) decides, with the
+      // oracle's rounding; the FP32 copy settles candidates away from it
+      if (ok && !(d2 < p.rlist2_lo))
+        ok = dist2_plain(sub_plain(b.x[j], xi), sub_plain(b.y[j], yi), sub_plain(b.z[j], zi)) < p.rlist2;
+      const unsigned m = (unsigned)(__ballot(ok) >> gbase) & ((1u << KB) - 1u);
+      const int pos = cnt + __popc(m & below);
+      if (ok && pos < cap) buf[pos] = j;
+      cnt += __popc(m);
     }
   }
   // (a wavefront's LDS accesses take effect in program order: only the
@@ -1216,8 +1254,9 @@ __device__ void build_staged(const Params &p, const Buffers &b, int64_t i, int l
 }
 
 // The staged build's kernel: dynamic LDS of kBlock / KB buffers of
-// Params::cap_slots * LPA words (launched where that fits kStageLdsMax).
-constexpr int kStageLdsMax = 64 * 1024;
+// Params::cap_slots * LPA words (launched where that fits kStageLdsMax,
+// which leaves room for the row tables within a block's 64 KiB).
+constexpr int kStageLdsMax = 60 * 1024;
 template <class R, int LPA>
 __global__ __launch_bounds__(kBlock) void k_build_staged(Params p, Buffers b, int32_t cond) {
   if (cond) {
@@ -1225,11 +1264,12 @@ __global__ __launch_bounds__(kBlock) void k_build_staged(Params p, Buffers b, in
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(reinterpret_cast<unsigned long long *>(&b.ctl->nbuild), 1ull);
   }
   extern __shared__ int stage[];
+  __shared__ int rowtab[(kBlock / KB) * 64];
   const int lane = (int)(threadIdx.x & (KB - 1));
   int *buf = stage + (size_t)(threadIdx.x / KB) * (size_t)(p.cap_slots * LPA);
   const int64_t per_pass = (int64_t)gridDim.x * (kBlock / KB);
   for (int64_t i = (int64_t)blockIdx.x * (kBlock / KB) + threadIdx.x / KB; i < p.ntot; i += per_pass)
-    if (b.group[i] != kPad) build_staged<R, LPA>(p, b, i, lane, buf);  // a lane group skips together
+    if (b.group[i] != kPad) build_staged<R, LPA>(p, b, i, lane, buf, rowtab);  // a lane group skips together
 }
 
 // In the mixed form (p.fold) the step's kick-drift is done here too.  The
