@@ -14,7 +14,8 @@ shape allows.  Checked here:
     parity tests' bar), and a burst on pruned lists of both forms runs;
   - a film 20 A thick and 518 A wide: its bins are ordered along a wide
     axis, so every atom keeps the 16-bit form; cells (bit-exact) and lists
-    against the oracle.
+    against the oracle;
+  - lists too long for the staged build's LDS take the direct build.
 """
 import numpy as np
 import pytest
@@ -152,3 +153,33 @@ def test_neighbours_over_several_scan_tiles():
     roff, ridx = O.neighbors(x, y, z, 8.1 + info["skin"])
     assert np.array_equal(off, roff)
     assert np.array_equal(idx, ridx)
+
+
+def test_long_lists_take_the_direct_build():
+    """A dense simple-cubic arrangement (1.5 A apart, up to ~930 neighbours
+    per atom within rc + skin): the lists outgrow what the staged build holds
+    in LDS (960 entries; overflow grows the capacity by half until they
+    fit), so they are built directly, each kept entry written from the
+    candidate loop.  Neighbour sets bit-exact and FP64 forces against the
+    oracle."""
+    O = _orc()
+    x, y, z = synth.gas(14, 1.5, 41, jitter=0.05)  # 2,744 atoms, 20 A across
+    n = len(x)
+    zero = np.zeros(n)
+    s = dict(x=x, y=y, z=z, vx=zero, vy=zero.copy(), vz=zero.copy(), group=np.zeros(n, np.uint8),
+             volume0=21.0 ** 3, area0=21.0 ** 2)
+    with P.System.from_state(s, T0=300.0, md=P.md_params(precision=0, lanes_per_atom=4, thermostat=0)) as g:
+        f = g.compute_forces()
+        off, idx = g.get_neighbors()
+        info = g.info()
+    print(f"\nlist capacity {info['list_capacity']}, entries per atom up to {int(np.diff(off).max())}")
+    assert info["list_capacity"] > 960 and info["list_index_bits"] == 16
+    roff, ridx = O.neighbors(x, y, z, 8.1 + info["skin"])
+    assert np.array_equal(off, roff)
+    assert np.array_equal(idx, ridx)
+    ref = O.forces(x, y, z, O.sc_params(), s["group"])
+    F = np.stack([ref["fx"], ref["fy"], ref["fz"]], 1)
+    G = np.stack([f["fx"], f["fy"], f["fz"]], 1)
+    frms = np.sqrt((F ** 2).sum(1).mean())
+    err = (np.linalg.norm(G - F, axis=1) / np.maximum(np.linalg.norm(F, axis=1), frms)).max()
+    assert err <= 1e-9
