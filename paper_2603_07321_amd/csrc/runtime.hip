@@ -664,12 +664,20 @@ static void sort_system(ptamd_system *s) {
 // Every m-th step is a rebuild point: its kick-drift checks whether the lists
 // last until the next point (P.trig_v covers m - 1 steps), and a conditional
 // build follows that runs only when some atom asked for it.  The lists stay
-// valid inside the graph without a return to the host.
-static GraphEntry &get_graph(ptamd_system *s, int K, bool with_build, int m) {
+// valid inside the graph without a return to the host.  lead: steps of the
+// same chunk launched directly before the graph (0, or 2 with the kernel
+// timing on), the first of which pruned the lists.
+static GraphEntry &get_graph(ptamd_system *s, int K, bool with_build, int m, int lead = 0) {
   // every launch-time flag captured in the graph is part of its key
   const int pe = s->P.inner ? s->prune_every : 0;
+  // After two direct steps, the first of which pruned, the graph need not
+  // prune at its start when its first pruning point, moved one rebuild point
+  // earlier, still comes within the pe m steps a pruned list serves (at
+  // chunk step (pe - 1) m + 1 <= pe m - 1); with pe = 1 it keeps the
+  // pruning pass at its start.
+  const bool shifted = lead == 2 && pe >= 2 && m > 1;
   const int key = 256 * K + 64 * pe + (s->P.inner ? 32 : 0) + (m > 1 ? 16 : 0) + (s->P.msum ? 8 : 0) +
-                  (s->P.top_free ? 4 : 0) + (s->P.conv ? 2 : 0) + (with_build ? 1 : 0);
+                  (s->P.top_free ? 4 : 0) + (s->P.conv ? 2 : 0) + (with_build ? 1 : 0) + (shifted ? 1 << 20 : 0);
   auto it = s->graphs.find(key);
   if (it != s->graphs.end()) return it->second;
   GraphEntry g;
@@ -687,7 +695,9 @@ static GraphEntry &get_graph(ptamd_system *s, int K, bool with_build, int m) {
   if (with_build) launch_build(s->P, s->B, s->precision, s->lpa, s->cap_stream);
   for (int32_t k = 0; k < K; ++k) {
     const bool point = k % m == m - 1;
-    const bool prune = k == 0 || (point && pe > 0 && ((k + 1) / m) % pe == 0);
+    const int pt = (k + 1) / m;  // rebuild points up to this one
+    const bool prune = shifted ? (point && pt % pe == pe - 1)
+                               : (k == 0 || (point && pe > 0 && pt % pe == 0));
     if (fold) {
       if (point) launch_build(s->P, s->B, s->precision, s->lpa, s->cap_stream, 1);
       launch_density(s->P, s->B, s->precision, s->lpa, k, s->cap_stream, prune);
@@ -721,7 +731,7 @@ static int chunk_graph_steps(int K, int nd) {
 static void prepare_graphs(ptamd_system *s) {
   s->P.inner = s->prune_every > 0 ? 1 : 0;
   for (int g = 1; g <= kMaxChunk; g += (g < 16 ? 1 : 8)) {
-    get_graph(s, g, false, kRebuildEvery);
+    get_graph(s, g, false, kRebuildEvery, s->timing ? 2 : 0);
     if (!s->timing) get_graph(s, g, true, kRebuildEvery);
   }
 }
@@ -948,7 +958,7 @@ static void run_burst(ptamd_system *s, int64_t n_steps, ptamd_averages *out, con
       if (K > nd) launch_set_base(s->B, step + nd, s->stream);
     }
     check_launch();
-    if (K > done) HIPCHK(hipGraphLaunch(get_graph(s, K - done, build && !timing, m).exec, s->stream));
+    if (K > done) HIPCHK(hipGraphLaunch(get_graph(s, K - done, build && !timing, m, done).exec, s->stream));
     st = chunk_stats(s, (timing && nd == 2) ? s->ntot * s->lpa / kBlock : 0);
     s->list_builds += s->h_ctl->nbuild - s->nbuild_seen;
     s->nbuild_seen = s->h_ctl->nbuild;

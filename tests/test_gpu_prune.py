@@ -131,3 +131,59 @@ def test_hot_system_runs_on_full_lists_where_rebuilds_are_every_step():
     assert dr <= 1e-8
     for k in ("ke", "pe", "szz"):
         assert avg[k] == pytest.approx(ravg[k], rel=1e-9, abs=1e-9), k
+
+
+def _run_timed(s, n, precision, prune_every, timed, lanes=4, T0=300.0):
+    md = P.md_params(precision=precision, lanes_per_atom=lanes, full_lists=0, prune_every=prune_every)
+    with P.System.from_state(s, T0=T0, md=md) as g:
+        if timed:
+            g.kernel_timing(reset=True)
+        avg = g.run_fast_md(n)[0]
+        st = g.get_state()
+        kt = g.kernel_timing() if timed else None
+        info = g.info()
+    return avg, st, kt, info
+
+
+@pytest.mark.parametrize("prune_every", [1, 2, 3])
+def test_fp64_timed_chunks_match_the_oracle(prune_every):
+    """With the kernel timing on, each chunk launches its first two steps
+    directly (the first prunes) and the rest as a graph whose pruning points
+    follow from there (with a pruning pass every 8 or 12 steps the graph's
+    first one comes a rebuild point early instead of at its start).  The
+    trajectory must meet the FP64 bars against the oracle as without the
+    timing."""
+    O = _orc()
+    s = _state(6, 0.05, 300.0, 57)
+    a_t, st_t, kt, info = _run_timed(s, 100, 0, prune_every, True)
+    a_u, st_u, _, _ = _run_timed(s, 100, 0, prune_every, False)
+    os_ = O.State(*(s[k].copy() for k in ("x", "y", "z", "vx", "vy", "vz", "group")), s["volume0"], s["area0"])
+    ravg, _ = O.run_burst(os_, O.sc_params(), O.md_params(), 100)
+    dr = max(np.abs(st_t[k] - getattr(os_, k)).max() for k in ("x", "y", "z"))
+    dv = max(np.abs(st_t[k] - getattr(os_, k)).max() for k in ("vx", "vy", "vz"))
+    print(f"\ntimed chunks, pruning every {4 * prune_every} steps: {kt['count']} timed steps, |dr| {dr:.2e} "
+          f"|dv| {dv:.2e}")
+    assert kt["count"] >= 1 and kt["force_event_ms"] > 0.0 and info["rollbacks"] == 0
+    assert info["prune_every"] == prune_every
+    assert dr <= 1e-8 and dv <= 1e-10
+    for k in ("ke", "pe", "szz", "tz"):
+        assert a_t[k] == pytest.approx(ravg[k], rel=1e-9, abs=1e-9), k
+        assert a_t[k] == pytest.approx(a_u[k], rel=1e-11, abs=1e-11), k
+
+
+@pytest.mark.parametrize("nc", [8, 33])
+def test_mixed_timed_chunks_match_untimed(nc):
+    """The same in the mixed form: folded (2,048 atoms) and, above 131,072
+    atoms (143,748), the three-kernel step the default workload runs; timed
+    and untimed runs agree to FP32 rounding."""
+    s = _state(nc, 0.05, 300.0, 58)
+    a_t, st_t, kt, info = _run_timed(s, 200, 1, 3, True)
+    a_u, st_u, _, info_u = _run_timed(s, 200, 1, 3, False)
+    dr = max(np.abs(st_t[k] - st_u[k]).max() for k in ("x", "y", "z"))
+    print(f"\ncube of {nc} cells, mixed, folded {info['folded']}: {kt['count']} timed steps, "
+          f"|dr| timed vs untimed {dr:.2e}")
+    assert info["folded"] == (1 if nc == 8 else 0) and info_u["folded"] == info["folded"]
+    assert kt["count"] >= 1 and info["rollbacks"] == 0 and info["prune_every"] == 3
+    assert dr <= 1e-5
+    for k in ("ke", "pe", "szz"):
+        assert a_t[k] == pytest.approx(a_u[k], rel=1e-6), k
