@@ -311,3 +311,44 @@ def test_invalid_run_arguments():
             g.run_fast_md(0)
         with pytest.raises(P.PtamdError):
             g.apply_strain_increment(0.5)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("sep", [2.9, 7.0, 12.0])
+def test_isolated_dimer(precision, sep):
+    """The smallest system the path takes: two mobile atoms on the x axis,
+    approaching each other, no fixed atoms, no thermostat.  At 2.9 A (near the
+    bond length) and 7 A (in the tail of the shifted potential) they interact;
+    at 12 A, beyond rc + skin, neither has a list entry: free flight, zero
+    energy.  FP64 meets the trajectory bars against the oracle; the mixed form
+    its FP32 rounding.  Each atom's force comes from its own list with the
+    separation negated exactly, so the total momentum stays zero."""
+    O = _orc()
+    z = np.zeros(2)
+    s = dict(x=np.array([0.0, sep]), y=z.copy(), z=z.copy(), vx=np.array([0.001, -0.001]), vy=z.copy(),
+             vz=z.copy(), group=np.zeros(2, np.uint8), volume0=1000.0, area0=0.0)
+    n = 200
+    md = P.md_params(precision=precision, thermostat=0, skin=1.5)
+    with P.System.from_state(s, T0=300.0, md=md) as g:
+        avg = g.run_fast_md(n)[0]
+        st = g.get_state()
+    os_ = O.State(*(s[k].copy() for k in ("x", "y", "z", "vx", "vy", "vz", "group")), s["volume0"], s["area0"])
+    ravg, _ = O.run_burst(os_, O.sc_params(), O.md_params(thermostat=0), n)
+    dr = max(np.abs(st[k] - getattr(os_, k)).max() for k in ("x", "y", "z"))
+    dv = max(np.abs(st[k] - getattr(os_, k)).max() for k in ("vx", "vy", "vz"))
+    print(f"\ndimer at {sep} A, precision {precision}: final separation {st['x'][1] - st['x'][0]:.6f} A, "
+          f"|dr| {dr:.2e} |dv| {dv:.2e}, pe {avg['pe']:.6e}")
+    assert abs(st["vx"][0] + st["vx"][1]) <= 1e-15
+    assert np.all(st["y"] == 0.0) and np.all(st["z"] == 0.0)
+    if sep > 8.1 + 1.5:
+        assert avg["pe"] == 0.0 and ravg["pe"] == 0.0
+    if precision == 0:
+        assert dr <= 1e-8 and dv <= 1e-10
+        # the device's global sums round each atom's value to 2^-36 eV
+        # (1.5e-11): with two atoms that alone is ~4e-9 of this kinetic energy
+        for k in ("ke", "pe", "szz"):
+            assert avg[k] == pytest.approx(ravg[k], rel=1e-9, abs=1e-10), k
+    else:
+        assert dr <= 1e-5 and dv <= 1e-7
+        for k in ("ke", "pe"):
+            assert avg[k] == pytest.approx(ravg[k], rel=1e-5, abs=1e-9), k
