@@ -145,8 +145,8 @@ def _run_timed(s, n, precision, prune_every, timed, lanes=4, T0=300.0):
     return avg, st, kt, info
 
 
-@pytest.mark.parametrize("prune_every", [1, 2, 3])
-def test_fp64_timed_chunks_match_the_oracle(prune_every):
+@pytest.mark.parametrize("prune_every,lanes", [(1, 4), (2, 4), (3, 4), (3, 16)])
+def test_fp64_timed_chunks_match_the_oracle(prune_every, lanes):
     """With the kernel timing on, each chunk launches its first two steps
     directly (the first prunes) and the rest as a graph whose pruning points
     follow from there (with a pruning pass every 8 or 12 steps the graph's
@@ -155,16 +155,16 @@ def test_fp64_timed_chunks_match_the_oracle(prune_every):
     timing."""
     O = _orc()
     s = _state(6, 0.05, 300.0, 57)
-    a_t, st_t, kt, info = _run_timed(s, 100, 0, prune_every, True)
-    a_u, st_u, _, _ = _run_timed(s, 100, 0, prune_every, False)
+    a_t, st_t, kt, info = _run_timed(s, 100, 0, prune_every, True, lanes=lanes)
+    a_u, st_u, _, _ = _run_timed(s, 100, 0, prune_every, False, lanes=lanes)
     os_ = O.State(*(s[k].copy() for k in ("x", "y", "z", "vx", "vy", "vz", "group")), s["volume0"], s["area0"])
     ravg, _ = O.run_burst(os_, O.sc_params(), O.md_params(), 100)
     dr = max(np.abs(st_t[k] - getattr(os_, k)).max() for k in ("x", "y", "z"))
     dv = max(np.abs(st_t[k] - getattr(os_, k)).max() for k in ("vx", "vy", "vz"))
-    print(f"\ntimed chunks, pruning every {4 * prune_every} steps: {kt['count']} timed steps, |dr| {dr:.2e} "
+    print(f"\ntimed chunks, {lanes} lanes, pruning every {4 * prune_every} steps: {kt['count']} timed steps, |dr| {dr:.2e} "
           f"|dv| {dv:.2e}")
     assert kt["count"] >= 1 and kt["force_event_ms"] > 0.0 and info["rollbacks"] == 0
-    assert info["prune_every"] == prune_every
+    assert info["prune_every"] == prune_every and info["lanes_per_atom"] == lanes
     assert dr <= 1e-8 and dv <= 1e-10
     for k in ("ke", "pe", "szz", "tz"):
         assert a_t[k] == pytest.approx(ravg[k], rel=1e-9, abs=1e-9), k
@@ -187,3 +187,32 @@ def test_mixed_timed_chunks_match_untimed(nc):
     assert dr <= 1e-5
     for k in ("ke", "pe", "szz"):
         assert a_t[k] == pytest.approx(a_u[k], rel=1e-6), k
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_timed_chunks_match_untimed(precision):
+    """A batch of three unequal cubes (one launch per kernel for all of them)
+    with the kernel timing on, as the batched workloads are timed: each
+    replica's averages and state agree with the untimed batch to rounding."""
+    descs = [P.lattice_desc(5, 200.0, 3), P.lattice_desc(7, 400.0, 4), P.lattice_desc(4, 300.0, 5)]
+    md = P.md_params(precision=precision, lanes_per_atom=4, full_lists=0, prune_every=2)
+    out = []
+    for timed in (True, False):
+        with P.System.batch(descs, md=md) as b:
+            if timed:
+                b.kernel_timing(reset=True)
+            b.apply_strain_increments([1e-4, -1e-4, 0.0])
+            avg = b.run_fast_md(150)
+            st = b.get_state()
+            kt = b.kernel_timing() if timed else None
+            info = b.info()
+        out.append((avg, st, kt, info))
+    (a_t, st_t, kt, info_t), (a_u, st_u, _, info_u) = out
+    dr = max(np.abs(st_t[k] - st_u[k]).max() for k in ("x", "y", "z"))
+    print(f"\nbatch of 3, precision {precision}: {kt['count']} timed steps, |dr| timed vs untimed {dr:.2e}")
+    assert kt["count"] >= 1 and info_t["rollbacks"] == 0 and info_u["rollbacks"] == 0
+    rel, dxm = (1e-9, 1e-9) if precision == 0 else (1e-6, 1e-5)
+    assert dr <= dxm
+    for r in range(3):
+        for k in ("ke", "pe", "szz", "tz"):
+            assert a_t[r][k] == pytest.approx(a_u[r][k], rel=rel, abs=rel), (r, k)
